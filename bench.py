@@ -1,0 +1,165 @@
+"""Benchmark: population TabuCol moves/s on one MI355X.
+
+Default workload (the configuration the headline metric is quoted on):
+G(500, 0.5) from seed 0, k = 49, population 8192, 100,000 tabu iterations
+per individual, 16-bit packed gamma/tabu table in LDS, 256 threads per
+workgroup.  One step = random population initialisation + one full TabuCol
+pass over the population (every kernel of the search path); the graph is
+uploaded once, before timing.  Step s uses initial-colouring seed
+1 + s so every step searches new individuals.
+
+Prints ONE JSON line (rank 0).  value = total tabu moves / timed wall time.
+roofline: algorithmic LDS bytes of the TabuCol kernel (the per-move byte
+model over the recorded counters) / its average duration measured with HIP
+events on the launch stream, against 256 CU x 128 B/clk x 2.4 GHz.
+cpu_baseline: the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+GNP500_BLOCK = 256
+GNP500_TABLE = "lds16"
+LDS_PEAK_GBS = 256 * 128 * 2.4  # GB/s: 256 CUs x 128 B/clk x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lds_bytes(st: np.ndarray, k: int, s_gamma: int = 2, s_tabu: int = 2, s_col: int = 2) -> float:
+    """Algorithmic LDS bytes of a TabuCol run from its counters.
+
+    Per iteration: C_t (k-1) (s_gamma + s_tabu) [candidate scan]
+                 + C_t (s_gamma + s_col)         [current colour and gamma]
+    per move:      deg(v*) (4 s_gamma + s_col)   [neighbour gamma updates]
+                 + s_tabu + s_col                [tabu entry, colour]
+    st columns: 0 moves, 2 sum C_t, 3 sum deg(v*).
+    """
+    moves, sum_c, sum_deg = st[:, 0].sum(), st[:, 2].sum(), st[:, 3].sum()
+    return float(sum_c * ((k - 1) * (s_gamma + s_tabu) + s_gamma + s_col)
+                 + sum_deg * (4 * s_gamma + s_col) + moves * (s_tabu + s_col))
+
+
+def hbm_bytes(st: np.ndarray) -> float:
+    """Algorithmic HBM bytes: the CSR row of v* (4 B per neighbour) per move."""
+    return float(4 * st[:, 3].sum())
+
+
+def cpu_baseline(g, k, T, seed, init_seed, count, threads):
+    import oracle
+    ids = np.arange(count, dtype=np.int32)
+    starts = oracle.init_random(g.n, k, count, seed=init_seed)
+    t0 = time.perf_counter()
+    r = oracle.tabucol_batch(g, starts, ids, k, T, seed=seed, nthreads=threads)
+    dt = time.perf_counter() - t0
+    moves = int(r["stats"][:, 0].sum())
+    return {"value": moves / dt, "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{count} individuals x {T} iterations of the same workload "
+                      f"({moves} moves in {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gnp500", choices=["gnp500", "gnp100"])
+    ap.add_argument("--block", type=int, default=GNP500_BLOCK)
+    ap.add_argument("--table", default=GNP500_TABLE)
+    ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
+              "the population shards by individual with no communication, see DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2109_05948_amd as dlm
+    from workloads import workload
+
+    w = workload(args.workload)
+    g, k, T = w.graphs[0], w.k[0], w.iters[0]
+    pop = args.pop or w.pop
+    G = dlm.Graph.from_csr(g)
+    dev = torch.device("cuda:0")
+    colors = torch.empty((pop, g.n), dtype=torch.int16, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(s, ev=None):
+        dlm.init_population(G, k, pop, seed=w.init_seed + s, colors=colors)
+        if ev:
+            ev[0].record(stream)
+        r = dlm.tabu_batch(G, colors, k, T, w.tabu_seed, block=args.block, table=args.table)
+        if ev:
+            ev[1].record(stream)
+        return r
+
+    for s in range(args.warmup):
+        log(f"warmup step {s}")
+        step(1000 + s)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    stats = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        r = step(s, evs[s])
+        stats.append(r["stats"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = torch.cat(stats).cpu().numpy()
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    moves = int(st[:, 0].sum())
+    log(f"timed {args.steps} steps in {dt:.3f} s; tabu kernel {kern_ms:.2f} ms/launch; "
+        f"moves {moves}; no-ops {int(st[:, 1].sum())}")
+
+    per_launch_lds = lds_bytes(st, k) / args.steps
+    per_launch_hbm = hbm_bytes(st) / args.steps
+    lds_gbs = per_launch_lds / (kern_ms * 1e-3) / 1e9
+    hbm_gbs = per_launch_hbm / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": moves / dt,
+        "unit": "moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": f"G(n={g.n}, p=0.5) seed 0", "k": k,
+                   "population": pop, "iters_per_individual": T, "block": args.block,
+                   "table": args.table, "parallelism": "population (one workgroup per individual)"},
+        "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": None,
+                     "kernel": "tabucol_kernel", "kernel_ms": kern_ms,
+                     "bytes_per_launch": per_launch_lds},
+        "roofline_hbm": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None},
+        "tabu_kernel_moves_per_s": moves / args.steps / (kern_ms * 1e-3),
+    }
+    if not args.no_cpu_baseline and args.workload == "gnp500":
+        threads = min(os.cpu_count() or 1, 16)
+        log(f"cpu baseline: oracle on {args.cpu_sample} individuals, {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(g, k, T, w.tabu_seed, w.init_seed, args.cpu_sample,
+                                           threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

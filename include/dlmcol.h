@@ -1,0 +1,250 @@
+/*
+ * dlmcol.h -- C ABI of the MI355X (gfx950) population graph-colouring hot
+ * path of the deep-learning guided memetic colouring method (Goudet, Grelier
+ * and Hao, "A deep learning guided memetic framework for graph coloring
+ * problems").
+ *
+ * Conventions for every call:
+ *   - Return value: DLM_OK (0) or a negative DLM_E_* status.  The message of
+ *     the last failure on the calling thread is returned by dlm_last_error().
+ *     On failure nothing has been launched after the failing check and the
+ *     contents of output buffers are unspecified.
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller; the
+ *     library never frees or keeps them after the call returns.  Pointers
+ *     named *_host are host pointers read synchronously during the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is asynchronous on that stream: outputs are valid once the
+ *     caller synchronises it.
+ *   - Colourings are int16 [count][n] row-major; colours are 0..k-1.
+ *   - Randomness is counter based (Philox4x32-10 keyed by the 64-bit seed), so
+ *     an individual's result depends only on (inputs, seed, its global index),
+ *     never on the population size, launch shape or table storage.
+ */
+#ifndef DLMCOL_H
+#define DLMCOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DLM_ABI_VERSION 1
+
+#define DLM_OK 0
+#define DLM_E_INVAL (-1)       /* bad argument (null pointer, size, range, CSR rule) */
+#define DLM_E_NOMEM (-2)       /* device allocation failed */
+#define DLM_E_HIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define DLM_E_UNSUPPORTED (-4) /* valid request beyond what this build supports */
+
+#define DLM_NSTATS 8 /* per-individual counters written by the tabu calls */
+
+/* Version of this ABI (DLM_ABI_VERSION of the build). */
+int dlm_abi_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* dlm_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Graph ingest.  The graph G = (V, E) of the colouring problems (Section 1 of
+ * the paper), shared read-only by every search in device memory (Section 2.2:
+ * the graph lives in global memory, shared by all tabu runs).
+ * ---------------------------------------------------------------------- */
+typedef struct dlm_graph dlm_graph; /* opaque, immutable after creation */
+
+/*
+ * Validate and upload an undirected simple graph in CSR form.
+ *   n            number of vertices, 1 <= n <= 32767
+ *   row_ptr_host int32[n+1], row_ptr[0] = 0, non-decreasing
+ *   col_idx_host int32[row_ptr[n]]: both directions of every edge, each row
+ *                strictly ascending, indices in [0, n), no self loops,
+ *                symmetric
+ *   weights_host int32[n] vertex weights w_v > 0 (weighted problem), or NULL
+ * On success *out owns device copies; release with dlm_graph_destroy.
+ * Errors: DLM_E_INVAL for any CSR rule broken, DLM_E_NOMEM, DLM_E_HIP.
+ */
+int dlm_graph_create(int32_t n, const int32_t* row_ptr_host, const int32_t* col_idx_host,
+                     const int32_t* weights_host, dlm_graph** out);
+int dlm_graph_destroy(dlm_graph* g);
+/* n, number of CSR entries (2|E|) and the maximum degree; any output may be NULL. */
+int dlm_graph_info(const dlm_graph* g, int32_t* n, int64_t* nnz, int32_t* max_deg);
+
+/* ------------------------------------------------------------------------
+ * Population initialisation.
+ *   DLM_INIT_RANDOM (k-COL, Section 2.7): colour of vertex v of individual i =
+ *     floor(w0 * k / 2^32), w0 = Philox(seed; ind_base+i, 0, v, 0x80000002).
+ *   DLM_INIT_GREEDY (WVCP, Section 2.1): vertices by weight descending, then
+ *     degree descending, then index; each takes a random already-used colour
+ *     that creates no conflict (uniform pick among them, Philox counter
+ *     (ind, 0, v, 0x80000008)), else opens a new colour numbered by creation
+ *     order.  k is not used in this mode; k_used_dev receives the number of
+ *     colours each individual used, and a search that follows needs k at
+ *     least their maximum.  Needs a weighted graph.
+ *   colors_dev  int16[pop][n] output
+ *   k_used_dev  int32[pop] output: colours used (greedy) or k (random); may
+ *               be NULL
+ * ---------------------------------------------------------------------- */
+#define DLM_INIT_RANDOM 0
+#define DLM_INIT_GREEDY 1
+int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, uint64_t seed,
+                        int32_t ind_base, int32_t mode, int16_t* colors_dev,
+                        int32_t* k_used_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Population TabuCol (k-COL local search, Section 2.7; TabuCol with the
+ * gamma table of its efficient implementation).  One workgroup per
+ * individual; each keeps the n x k table gamma[v][c] = number of neighbours
+ * of v coloured c, plus the tabu expiry of every (v, c).
+ *
+ * Iteration t (t = 0, 1, ...) while t < max_iters and f > 0:
+ *   candidates: (v, c) with gamma[v][col v] > 0 (v in conflict), c != col v,
+ *     delta = gamma[v][c] - gamma[v][col v];
+ *   admissible: not tabu (expiry <= t) or f + delta < f_best (aspiration);
+ *   choice: lexicographic minimum of (delta, h, v, c), h = word 0 of
+ *     Philox(seed; ind, t, v, c); no admissible move => no-op iteration;
+ *   move: col v = c, f += delta, (v, old colour) tabu until
+ *     t + L + min(floor(ten_num * f / ten_den), 32757) with
+ *     L = floor(w0 * ten_rand / 2^32), w0 = Philox(seed; ind, t, 0, 0x80000001);
+ *   the best colouring met (smallest f) is kept.
+ * ---------------------------------------------------------------------- */
+#define DLM_TABLE_AUTO 0       /* packed 16-bit in LDS if it fits, else global */
+#define DLM_TABLE_LDS16 1      /* 32-bit word per (v,c): gamma 16 bits | tabu 16 bits, LDS */
+#define DLM_TABLE_LDS32 2      /* 64-bit word per (v,c): gamma int32 | tabu expiry, LDS */
+#define DLM_TABLE_GLOBAL16 3   /* packed 16-bit words in device memory (large n*k) */
+
+typedef struct dlm_tabu_params {
+  int32_t k;          /* colours, 1 <= k <= 32767 */
+  int32_t max_iters;  /* iteration budget T, 0 <= T <= 2^30 */
+  int32_t ten_num;    /* tenure slope numerator (6 for 0.6 f) */
+  int32_t ten_den;    /* tenure slope denominator (10), > 0 */
+  int32_t ten_rand;   /* L uniform in [0, ten_rand), 1..1024 */
+  int32_t ind_base;   /* global index of row 0 of the population */
+  uint64_t seed;      /* Philox key */
+  int32_t block;      /* threads per workgroup: 0 = auto, else 64, 128, 256, 512 or 1024 */
+  int32_t table;      /* DLM_TABLE_* storage of the n x k table */
+  int32_t trace_cap;  /* records per individual in trace_dev (0 = none) */
+  int32_t reserved;   /* must be 0 */
+} dlm_tabu_params;
+
+/*
+ * Run TabuCol on every individual of a population.
+ *   pop          number of individuals (0 is a no-op)
+ *   colors_dev   int16[pop][n]: in = start colouring S^O, out = best S'
+ *   f_best_dev   int32[pop]: conflicts of the returned colouring
+ *   iters_dev    int32[pop]: iterations run (stops early at f = 0)
+ *   stats_dev    int64[pop][DLM_NSTATS] or NULL: 0 moves, 1 no-ops, 2 sum over
+ *                iterations of the number of conflicting vertices scanned,
+ *                3 sum over moves of deg(v*), 4 iterations whose minimum
+ *                delta was shared by >= 2 admissible moves, 5 tenure-cap hits
+ *   hash_dev     uint64[pop] or NULL: FNV-1a (64-bit) over the move records
+ *                (v | c << 16 | (uint32)f_after << 32); a no-op records
+ *                v = c = 0xffff
+ *   trace_dev    int32[pop][trace_cap][2] or NULL: {v | c << 16, f_after} of
+ *                the first trace_cap iterations
+ * A start colouring holding a colour outside [0, k) is left untouched and its
+ * individual gets f_best = iters = -1 (its stats and hash are not written).
+ * Errors: DLM_E_INVAL (arguments),
+ * DLM_E_UNSUPPORTED (table does not fit the requested storage),
+ * DLM_E_NOMEM (global table workspace), DLM_E_HIP.
+ */
+int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                   int16_t* colors_dev, int32_t* f_best_dev, int32_t* iters_dev,
+                   int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Weighted colouring (WVCP): the iterated feasible/infeasible tabu search of
+ * Section 2.2 and Algorithm 2, one workgroup per individual.
+ *
+ * Round r (r = 0..rounds-1) runs iters_per_round iterations minimising
+ * g = (f_w << shift) + phi * c, f_w = sum over classes of the largest weight
+ * (eq. (score_WVCP)), c = conflicting edges (eq. (AFISA_score) with phi in
+ * fixed point, `shift` fractional bits).  phi_0 = floor(k * max_w * 2^shift /
+ * (2 n)); after a round whose best-g state is legal phi is halved, else
+ * doubled (at most 2^30); the last round uses phi = (2 max_w) << shift.
+ * Moves: every (v, c), c != col v; admissible if v is not frozen or g + delta
+ * < best g of the round; choice = lexicographic minimum of (delta g, h, v, c),
+ * h = word 0 of Philox(seed; ind, t, v, c), t counting on across rounds; the
+ * moved vertex is frozen until t + L + floor(frz_num * n / frz_den), L =
+ * floor(w0 * ten_rand / 2^32), w0 = Philox(seed; ind, t, 0, 0x80000001).
+ * Each round restarts from the previous round's best-g state.
+ *   colors_dev     int16[pop][n]: in = start, out = best legal colouring met
+ *                  (or the last round's best-g state if none was legal)
+ *   best_legal_dev int32[pop]: its f_w, 0x7fffffff if no legal colouring
+ *                  was met, -1 if the start held a colour outside [0, k)
+ *   stats_dev      int64[pop][DLM_NSTATS] or NULL: 0 moves, 1 no-ops,
+ *                  2 sum deg(v*), 3 tie iterations, 4 rounds whose best-g
+ *                  state is legal, 5 final phi
+ *   hash_dev       uint64[pop] or NULL: FNV-1a over (v, c, g >> shift)
+ * Needs a weighted graph.  Errors: DLM_E_INVAL, DLM_E_UNSUPPORTED (LDS),
+ * DLM_E_HIP.
+ * ---------------------------------------------------------------------- */
+typedef struct dlm_wvcp_params {
+  int32_t k;               /* colours available, 1..32767 */
+  int32_t iters_per_round; /* nbIter_TS (10 n in the paper's setting) */
+  int32_t rounds;          /* maxLSIters (10) */
+  int32_t ten_rand;        /* L uniform in [0, ten_rand), 1..1024 */
+  int32_t frz_num;         /* freeze slope numerator (2 for 0.2 |V|) */
+  int32_t frz_den;         /* freeze slope denominator (10) */
+  int32_t shift;           /* fractional bits of phi, 0..16 (10) */
+  int32_t ind_base;        /* global index of row 0 */
+  uint64_t seed;           /* Philox key */
+  int32_t block;           /* threads per workgroup: 0 = auto, 64, 128, 256 or 512 */
+  int32_t reserved;        /* must be 0 */
+} dlm_wvcp_params;
+
+int dlm_wvcp_batch(const dlm_graph* g, const dlm_wvcp_params* p, int32_t pop,
+                   int16_t* colors_dev, int32_t* best_legal_dev, int64_t* stats_dev,
+                   uint64_t* hash_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Scores (eq. (f) of Section 2.7 and eq. (score_WVCP) of Section 1).
+ *   conflicts_dev int32[count]: monochromatic edges of each colouring
+ *   wscore_dev    int32[count] or NULL: sum over colour classes of the largest
+ *                 vertex weight (needs a weighted graph)
+ * A colouring holding a colour outside [0, k) gets -1 in both outputs.
+ * ---------------------------------------------------------------------- */
+int dlm_evaluate(const dlm_graph* g, int32_t k, const int16_t* colors_dev, int32_t count,
+                 int32_t* conflicts_dev, int32_t* wscore_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Greedy partition crossover, GPX (Sections 1 and 2.6: the offspring
+ * inherits alternately the largest remaining colour class of each parent;
+ * the crossover is asymmetric, the individual being the first parent).
+ * Child j of pair p (child id c = child_base + p * per_pair + j) is built
+ * from A = parents[pairs[p][0]] (first) and B = parents[pairs[p][1]]: step
+ * l = 0..k-1 takes A when l is even and B when l is odd, picks the class of
+ * that parent with the most still-unassigned vertices (ties: smallest word 0
+ * of Philox(seed; c, l, u, 0x80000007) with u the lowest unassigned vertex
+ * of the class, then smallest u) and gives its unassigned vertices colour l.
+ * Vertices left after k steps get floor(w0 * k / 2^32), w0 =
+ * Philox(seed; c, 0, v, 0x80000003).
+ *   parents_dev  int16[pop][n], colours in [0, k)
+ *   pairs_dev    int32[npairs][2], indices in [0, pop)
+ *   children_dev int16[npairs * per_pair][n] output; a child whose pair
+ *                index or parent colour is out of range is all -1
+ * ---------------------------------------------------------------------- */
+int dlm_gpx_batch(const dlm_graph* g, int32_t k, const int16_t* parents_dev, int32_t pop,
+                  const int32_t* pairs_dev, int32_t npairs, int32_t per_pair, uint64_t seed,
+                  uint32_t child_base, int16_t* children_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Offspring selection (eq. (select_cross) of Section 2.6 taken
+ * population-wide): keep `keep` of `count` candidates.
+ *   DLM_SELECT_TOP (learned loop): the smallest predicted scores, ties by
+ *     index (NaN ranks last);
+ *   DLM_SELECT_RANDOM (plain loop): the smallest word 0 of
+ *     Philox(seed; i, gen, 0, 0x80000006), ties by index; scores unused.
+ *   scores_dev   float[count] (may be NULL in random mode)
+ *   idx_out_dev  int32[keep] output: selected indices in rank order
+ *   workspace_dev  caller-owned scratch of 8 * count bytes
+ * ---------------------------------------------------------------------- */
+#define DLM_SELECT_TOP 0
+#define DLM_SELECT_RANDOM 1
+int dlm_select(const float* scores_dev, int32_t count, int32_t keep, int32_t mode, uint64_t seed,
+               uint32_t gen, int32_t* idx_out_dev, void* workspace_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DLMCOL_H */

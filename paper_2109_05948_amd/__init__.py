@@ -1,0 +1,19 @@
+"""MI355X (gfx950) population graph-colouring hot path.
+
+The search runs in ``libdlmcol.so`` (hand-written HIP kernels behind the C
+ABI declared in ``include/dlmcol.h``); this package only marshals
+arguments.  Import fails loudly when the library has not been built.
+"""
+from ._abi import (  # noqa: F401
+    DlmError,
+    Graph,
+    NSTATS,
+    abi_version,
+    evaluate,
+    gpx_batch,
+    select,
+    init_population,
+    lib,
+    tabu_batch,
+    wvcp_batch,
+)

@@ -1,0 +1,257 @@
+"""ctypes binding of libdlmcol.so: argument marshalling only.
+
+Every call maps one-to-one onto a ``dlm_*`` entry point of
+``include/dlmcol.h``.  torch is used for device memory (tensors' data
+pointers) and streams (``torch.cuda.current_stream().cuda_stream``); every
+step of the search runs in the library's HIP kernels.  There is no fallback:
+if the library is missing or a call fails, a Python exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdlmcol.so")
+_lock = threading.Lock()
+_lib = None
+
+NSTATS = 8
+DLM_OK = 0
+TABLES = {"auto": 0, "lds16": 1, "lds32": 2, "global16": 3}
+INIT_MODES = {"random": 0, "greedy": 1}
+
+EXPORTS = [
+    "dlm_abi_version", "dlm_last_error", "dlm_graph_create", "dlm_graph_destroy", "dlm_graph_info",
+    "dlm_init_population", "dlm_tabu_batch", "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
+    "dlm_wvcp_batch",
+]
+
+
+class DlmError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} returned {code}: {msg}")
+        self.code = code
+
+
+class TabuParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("max_iters", C.c_int32), ("ten_num", C.c_int32),
+                ("ten_den", C.c_int32), ("ten_rand", C.c_int32), ("ind_base", C.c_int32),
+                ("seed", C.c_uint64), ("block", C.c_int32), ("table", C.c_int32),
+                ("trace_cap", C.c_int32), ("reserved", C.c_int32)]
+
+
+def lib():
+    """Load libdlmcol.so (never builds it; see paper_2109_05948_amd.build)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  "`python -m paper_2109_05948_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+            L.dlm_abi_version.restype = C.c_int
+            L.dlm_last_error.restype = C.c_char_p
+            L.dlm_graph_create.argtypes = [I32, P, P, P, C.POINTER(P)]
+            L.dlm_graph_destroy.argtypes = [P]
+            L.dlm_graph_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I32)]
+            L.dlm_init_population.argtypes = [P, I32, I32, U64, I32, I32, P, P, P]
+            L.dlm_tabu_batch.argtypes = [P, C.POINTER(TabuParams), I32, P, P, P, P, P, P, P]
+            L.dlm_evaluate.argtypes = [P, I32, P, I32, P, P, P]
+            L.dlm_gpx_batch.argtypes = [P, I32, P, I32, P, I32, I32, U64, C.c_uint32, P, P]
+            L.dlm_select.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P, P]
+            L.dlm_wvcp_batch.argtypes = [P, C.c_void_p, I32, P, P, P, P, P]
+            for name in EXPORTS:
+                getattr(L, name)
+            _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != DLM_OK:
+        raise DlmError(fn, rc, lib().dlm_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def abi_version() -> int:
+    return int(lib().dlm_abi_version())
+
+
+class Graph:
+    """dlm_graph: a validated CSR graph resident in device memory."""
+
+    def __init__(self, n: int, row_ptr, col_idx, weights=None):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
+        h = C.c_void_p()
+        _check("dlm_graph_create", lib().dlm_graph_create(n, _ptr(rp), _ptr(ci), _ptr(w), C.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.weighted = w is not None
+
+    @classmethod
+    def from_csr(cls, g) -> "Graph":
+        """From any object with n, row_ptr, col_idx and (optional) weights."""
+        return cls(g.n, g.row_ptr, g.col_idx, getattr(g, "weights", None))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> tuple[int, int, int]:
+        n, nnz, md = C.c_int32(), C.c_int64(), C.c_int32()
+        _check("dlm_graph_info", lib().dlm_graph_info(self._h, C.byref(n), C.byref(nnz), C.byref(md)))
+        return n.value, nnz.value, md.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dlm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_population(graph: Graph, k: int, pop: int, seed: int, ind_base: int = 0,
+                    mode: str = "random", colors: torch.Tensor | None = None,
+                    k_used: torch.Tensor | None = None, stream=None):
+    """dlm_init_population -> (colors int16 [pop, n], k_used int32 [pop])."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if colors is None:
+        colors = torch.empty((pop, graph.n), dtype=torch.int16, device=dev)
+    if k_used is None:
+        k_used = torch.empty((pop,), dtype=torch.int32, device=dev)
+    _dev(colors, torch.int16, "colors")
+    _dev(k_used, torch.int32, "k_used")
+    _check("dlm_init_population",
+           lib().dlm_init_population(graph.handle, k, pop, seed & (2**64 - 1), ind_base,
+                                     INIT_MODES[mode], _ptr(colors), _ptr(k_used), _stream(stream)))
+    return colors, k_used
+
+
+def tabu_batch(graph: Graph, colors: torch.Tensor, k: int, max_iters: int, seed: int,
+               ind_base: int = 0, ten_num: int = 6, ten_den: int = 10, ten_rand: int = 10,
+               block: int = 0, table: str = "auto", stats: bool = True, hashes: bool = True,
+               trace_cap: int = 0, out: dict | None = None, stream=None) -> dict:
+    """dlm_tabu_batch on every row of ``colors`` (modified in place to the best colouring)."""
+    _dev(colors, torch.int16, "colors")
+    pop = colors.shape[0]
+    if colors.dim() != 2 or colors.shape[1] != graph.n:
+        raise ValueError(f"colors must be [pop, {graph.n}]")
+    dev = colors.device
+    o = out if out is not None else {}
+    if "f_best" not in o:
+        o["f_best"] = torch.empty(pop, dtype=torch.int32, device=dev)
+        o["iters"] = torch.empty(pop, dtype=torch.int32, device=dev)
+        o["stats"] = torch.empty((pop, NSTATS), dtype=torch.int64, device=dev) if stats else None
+        o["hash"] = torch.empty(pop, dtype=torch.int64, device=dev) if hashes else None
+        o["trace"] = (torch.empty((pop, trace_cap, 2), dtype=torch.int32, device=dev)
+                      if trace_cap else None)
+    prm = TabuParams(k, max_iters, ten_num, ten_den, ten_rand, ind_base, seed & (2**64 - 1),
+                     block, TABLES[table], trace_cap, 0)
+    _check("dlm_tabu_batch",
+           lib().dlm_tabu_batch(graph.handle, C.byref(prm), pop, _ptr(colors), _ptr(o["f_best"]),
+                                _ptr(o["iters"]), _ptr(o.get("stats")), _ptr(o.get("hash")),
+                                _ptr(o.get("trace")), _stream(stream)))
+    o["colors"] = colors
+    return o
+
+
+def evaluate(graph: Graph, colors: torch.Tensor, k: int, weighted: bool = False, stream=None):
+    """dlm_evaluate -> (conflicts int32 [count], wscore int32 [count] or None)."""
+    _dev(colors, torch.int16, "colors")
+    cnt = colors.shape[0]
+    conf = torch.empty(cnt, dtype=torch.int32, device=colors.device)
+    ws = torch.empty(cnt, dtype=torch.int32, device=colors.device) if weighted else None
+    _check("dlm_evaluate", lib().dlm_evaluate(graph.handle, k, _ptr(colors), cnt, _ptr(conf),
+                                              _ptr(ws), _stream(stream)))
+    return conf, ws
+
+
+def gpx_batch(graph: Graph, k: int, parents: torch.Tensor, pairs: torch.Tensor, per_pair: int,
+              seed: int, child_base: int = 0, children: torch.Tensor | None = None, stream=None):
+    """dlm_gpx_batch -> children int16 [npairs * per_pair, n]."""
+    _dev(parents, torch.int16, "parents")
+    _dev(pairs, torch.int32, "pairs")
+    npairs = pairs.shape[0]
+    if children is None:
+        children = torch.empty((npairs * per_pair, graph.n), dtype=torch.int16,
+                               device=parents.device)
+    _dev(children, torch.int16, "children")
+    _check("dlm_gpx_batch",
+           lib().dlm_gpx_batch(graph.handle, k, _ptr(parents), parents.shape[0], _ptr(pairs),
+                               npairs, per_pair, seed & (2**64 - 1), child_base & 0xffffffff,
+                               _ptr(children), _stream(stream)))
+    return children
+
+
+def select(scores: torch.Tensor | None, count: int, keep: int, mode: str = "top", seed: int = 0,
+           gen: int = 0, stream=None) -> torch.Tensor:
+    """dlm_select -> int32 [keep] indices in rank order ("top" or "random")."""
+    dev = scores.device if scores is not None else torch.device("cuda", torch.cuda.current_device())
+    if scores is not None:
+        _dev(scores, torch.float32, "scores")
+    out = torch.empty(keep, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(count, 1), dtype=torch.int64, device=dev)
+    _check("dlm_select", lib().dlm_select(_ptr(scores), count, keep, {"top": 0, "random": 1}[mode],
+                                          seed & (2**64 - 1), gen & 0xffffffff, _ptr(out), _ptr(ws),
+                                          _stream(stream)))
+    return out
+
+
+class WvcpParams(C.Structure):
+    _fields_ = [("k", C.c_int32), ("iters_per_round", C.c_int32), ("rounds", C.c_int32),
+                ("ten_rand", C.c_int32), ("frz_num", C.c_int32), ("frz_den", C.c_int32),
+                ("shift", C.c_int32), ("ind_base", C.c_int32), ("seed", C.c_uint64),
+                ("block", C.c_int32), ("reserved", C.c_int32)]
+
+
+def wvcp_batch(graph: Graph, colors: torch.Tensor, k: int, iters_per_round: int, rounds: int,
+               seed: int, ind_base: int = 0, ten_rand: int = 10, frz_num: int = 2,
+               frz_den: int = 10, shift: int = 10, block: int = 0, stream=None) -> dict:
+    """dlm_wvcp_batch on every row of ``colors`` (in place: best legal colouring)."""
+    _dev(colors, torch.int16, "colors")
+    pop = colors.shape[0]
+    if colors.dim() != 2 or colors.shape[1] != graph.n:
+        raise ValueError(f"colors must be [pop, {graph.n}]")
+    dev = colors.device
+    o = {"best_legal": torch.empty(pop, dtype=torch.int32, device=dev),
+         "stats": torch.empty((pop, NSTATS), dtype=torch.int64, device=dev),
+         "hash": torch.empty(pop, dtype=torch.int64, device=dev)}
+    prm = WvcpParams(k, iters_per_round, rounds, ten_rand, frz_num, frz_den, shift, ind_base,
+                     seed & (2**64 - 1), block, 0)
+    _check("dlm_wvcp_batch",
+           lib().dlm_wvcp_batch(graph.handle, C.byref(prm), pop, _ptr(colors),
+                                _ptr(o["best_legal"]), _ptr(o["stats"]), _ptr(o["hash"]),
+                                _stream(stream)))
+    o["colors"] = colors
+    return o

@@ -1,0 +1,160 @@
+// Shared host/device helpers of the gfx950 colouring library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/dlmcol.h"
+
+namespace dlm {
+
+constexpr int kWave = 64;
+constexpr uint32_t kDomTenure = 0x80000001u;
+constexpr uint32_t kDomInit = 0x80000002u;
+constexpr uint32_t kDomGpxFill = 0x80000003u;
+constexpr uint32_t kDomSelect = 0x80000006u;
+constexpr uint32_t kDomGpxTie = 0x80000007u;
+constexpr uint32_t kDomGreedy = 0x80000008u;
+constexpr int kTenureCap = 32757;  // cap of the floor(num * f / den) tenure term
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications; key (k0, k1) = (low, high word of the seed),
+// bumped by the Weyl constants after every round.  Returns word 0 only
+// unless all four are asked for.
+struct Key {
+  uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed) {
+  return Key{static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+}
+
+__device__ __forceinline__ uint4 philox4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                         Key key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(x0, x1, x2, x3);
+}
+
+__device__ __forceinline__ uint32_t philox_w0(uint32_t x0, uint32_t x1, uint32_t x2,
+                                              uint32_t x3, Key key) {
+  return philox4(x0, x1, x2, x3, key).x;
+}
+
+// uniform integer in [0, K) from a 32-bit word: floor(x * K / 2^32)
+__host__ __device__ __forceinline__ uint32_t lemire(uint32_t x, uint32_t K) {
+  return static_cast<uint32_t>((static_cast<uint64_t>(x) * K) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 reductions on DPP lane moves.  Every lane of the wave must be active.
+// After quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and
+// row_mirror each lane holds the reduction of its 16-lane row; the four row
+// results are combined on the scalar unit.  The result is wave-uniform.
+namespace dpp {
+constexpr int kXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141; // row_half_mirror
+constexpr int kMirror = 0x140;     // row_mirror
+}  // namespace dpp
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t x) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(static_cast<int>(x), static_cast<int>(x), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_mov64(uint64_t x) {
+  const uint32_t lo = dpp_mov<CTRL>(static_cast<uint32_t>(x));
+  const uint32_t hi = dpp_mov<CTRL>(static_cast<uint32_t>(x >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
+  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), lane));
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+  return (static_cast<uint64_t>(readlane(static_cast<uint32_t>(x >> 32), lane)) << 32) |
+         readlane(static_cast<uint32_t>(x), lane);
+}
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+  x = umin64(x, dpp_mov64<dpp::kXor1>(x));
+  x = umin64(x, dpp_mov64<dpp::kXor2>(x));
+  x = umin64(x, dpp_mov64<dpp::kHalfMirror>(x));
+  x = umin64(x, dpp_mov64<dpp::kMirror>(x));
+  return umin64(umin64(readlane64(x, 0), readlane64(x, 16)),
+                umin64(readlane64(x, 32), readlane64(x, 48)));
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+  x += dpp_mov<dpp::kXor1>(x);
+  x += dpp_mov<dpp::kXor2>(x);
+  x += dpp_mov<dpp::kHalfMirror>(x);
+  x += dpp_mov<dpp::kMirror>(x);
+  return readlane(x, 0) + readlane(x, 16) + readlane(x, 32) + readlane(x, 48);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, dpp_mov<dpp::kXor1>(x));
+  x = max(x, dpp_mov<dpp::kXor2>(x));
+  x = max(x, dpp_mov<dpp::kHalfMirror>(x));
+  x = max(x, dpp_mov<dpp::kMirror>(x));
+  return max(max(readlane(x, 0), readlane(x, 16)), max(readlane(x, 32), readlane(x, 48)));
+}
+
+__host__ __device__ constexpr uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
+
+// FNV-1a over 64-bit move records
+constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
+constexpr uint64_t kFnvPrime = 0x100000001b3ull;
+__device__ __forceinline__ uint64_t fnv_step(uint64_t h, uint32_t v, uint32_t c, int32_t f) {
+  const uint64_t x = static_cast<uint64_t>(v & 0xffffu) | (static_cast<uint64_t>(c & 0xffffu) << 16) |
+                     (static_cast<uint64_t>(static_cast<uint32_t>(f)) << 32);
+  return (h ^ x) * kFnvPrime;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side error plumbing.
+int set_error(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+int device_lds_limit();  // max dynamic LDS bytes per workgroup on the current device
+int device_cu_count();
+
+#define DLM_HIP(call)                                    \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::dlm::hip_fail(e_, #call); \
+  } while (0)
+
+}  // namespace dlm
+
+struct dlm_graph {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  int32_t max_deg = 0;
+  int32_t max_w = 0;
+  int device = 0;
+  int32_t* row_ptr = nullptr;  // device int32[n+1]
+  int32_t* col_idx = nullptr;  // device int32[nnz]
+  int32_t* erow = nullptr;     // device int32[nnz]: source vertex of each CSR entry
+  int32_t* weights = nullptr;  // device int32[n] or null
+};

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every symbol include/dlmcol.h
+declares; argument checks that fail before any device work behave as the
+header states.  No compute call is made here (no GPU in this container)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dlmcol.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dlm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2109_05948_amd import _abi
+    return _abi.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    syms = declared_symbols()
+    assert "dlm_tabu_batch" in syms and len(syms) >= 8
+    for s in syms:
+        assert hasattr(L, s), s
+    from paper_2109_05948_amd import _abi
+    assert set(_abi.EXPORTS) <= set(syms)
+
+
+def test_version_and_error(L):
+    assert L.dlm_abi_version() == 1
+    assert isinstance(L.dlm_last_error(), bytes)
+
+
+@pytest.mark.parametrize("case", ["asym", "loop", "unsorted", "range", "n0", "weight0"])
+def test_graph_validation_rejects(L, case):
+    from paper_2109_05948_amd import _abi
+    n = 4
+    rp = np.array([0, 1, 2, 3, 4], np.int32)
+    ci = np.array([1, 0, 3, 2], np.int32)
+    w = None
+    if case == "asym":
+        rp = np.array([0, 1, 1, 1, 1], np.int32)
+        ci = np.array([1], np.int32)
+    elif case == "loop":
+        ci = np.array([0, 0, 3, 2], np.int32)
+    elif case == "unsorted":
+        rp = np.array([0, 2, 3, 4, 4], np.int32)
+        ci = np.array([2, 1, 0, 0], np.int32)
+    elif case == "range":
+        ci = np.array([1, 0, 3, 7], np.int32)
+    elif case == "n0":
+        n = 0
+    elif case == "weight0":
+        w = np.array([1, 0, 2, 3], np.int32)
+    with pytest.raises(_abi.DlmError) as e:
+        _abi.Graph(n, rp, ci, w)
+    assert e.value.code == -1
+    assert len(L.dlm_last_error()) > 0
+
+
+def test_null_arguments(L):
+    from paper_2109_05948_amd import _abi
+    prm = _abi.TabuParams(18, 10, 6, 10, 10, 0, 1, 0, 0, 0, 0)
+    assert L.dlm_tabu_batch(None, C.byref(prm), 1, None, None, None, None, None, None, None) == -1
+    assert L.dlm_graph_info(None, None, None, None) == -1
+    assert L.dlm_evaluate(None, 2, None, 1, None, None, None) == -1
+    assert L.dlm_init_population(None, 2, 1, 0, 0, 0, None, None, None) == -1
