@@ -153,6 +153,57 @@ int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
                    int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Uneven batches: the populations of many graphs (any mix of n, k and
+ * iteration budgets) searched by one persistent launch.  Each item is a
+ * dlm_tabu_batch call in all but the launch: same search, same outputs,
+ * bit-identical results.  Work items (graph, individual) are taken
+ * longest-first from an atomic queue by a grid sized to the device's
+ * resident capacity; graphs whose table fits the LDS budget use the LDS16
+ * table, the others the device-memory table.  A plan captures the queue
+ * reset and the persistent kernel into a hipGraph once; each launch replays
+ * it on the caller's stream and searches whatever the item buffers hold.
+ * The plan keeps the item pointers: buffers and graphs must outlive it.
+ * ---------------------------------------------------------------------- */
+typedef struct dlm_multi_item {
+  const dlm_graph* g;
+  int32_t k, max_iters, pop, ind_base;     /* as in dlm_tabu_params */
+  int32_t ten_num, ten_den, ten_rand, reserved;
+  uint64_t seed;
+  int16_t* colors_dev;   /* int16[pop][n], in: start, out: best */
+  int32_t* f_best_dev;   /* int32[pop] */
+  int32_t* iters_dev;    /* int32[pop] */
+  int64_t* stats_dev;    /* int64[pop][DLM_NSTATS] or NULL */
+  uint64_t* hash_dev;    /* uint64[pop] or NULL */
+} dlm_multi_item;
+
+typedef struct dlm_multi_config {
+  int32_t block;       /* threads per workgroup: 0 = 256, else 64, 128, 256 or 512 */
+  int32_t lds_budget;  /* LDS bytes a graph's table may use (0 = device maximum) */
+} dlm_multi_config;
+
+typedef struct dlm_multi_plan dlm_multi_plan;
+
+int dlm_multi_plan_create(const dlm_multi_item* items, int32_t count, const dlm_multi_config* cfg,
+                          void* stream, dlm_multi_plan** out);
+int dlm_multi_plan_launch(dlm_multi_plan* plan, void* stream);
+/* grid size, dynamic LDS bytes, graphs on the device-memory table, items */
+int dlm_multi_plan_info(const dlm_multi_plan* plan, int32_t* grid, int32_t* lds_bytes,
+                        int32_t* n_global, int32_t* total_items);
+int dlm_multi_plan_destroy(dlm_multi_plan* plan);
+
+/*
+ * Autotuner: times every (block in {64,128,256,512}) x (LDS budget in
+ * {1/4, 1/2, 1} of the device maximum) on scratch copies of the items'
+ * colourings with at most calib_iters iterations per individual, and
+ * returns the configuration with the most iterations per second in *best.
+ * rates (float[12] or NULL) receives every candidate's rate in that order.
+ * Results are cached per device and item shapes (ignored when rates is
+ * given).  The items' own buffers are not modified.  Synchronises stream.
+ */
+int dlm_multi_autotune(const dlm_multi_item* items, int32_t count, int32_t calib_iters,
+                       dlm_multi_config* best, float* rates, void* stream);
+
+/* ------------------------------------------------------------------------
  * Weighted colouring (WVCP): the iterated feasible/infeasible tabu search of
  * Section 2.2 and Algorithm 2, one workgroup per individual.
  *
@@ -243,6 +294,96 @@ int dlm_gpx_batch(const dlm_graph* g, int32_t k, const int16_t* parents_dev, int
 #define DLM_SELECT_RANDOM 1
 int dlm_select(const float* scores_dev, int32_t count, int32_t keep, int32_t mode, uint64_t seed,
                uint32_t gen, int32_t* idx_out_dev, void* workspace_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Device steps of one memetic generation (Algorithm 1) in the simplified
+ * form of this build: random partner pairing, offspring gather, target
+ * standardisation for the scorer, and the (mu + lambda) population update
+ * that stands in for the paper's distance-based update (Section 2.5).
+ * ---------------------------------------------------------------------- */
+
+/* dst[r] = src[idx[r]] for r < count (rows of n int16); a row whose index is
+ * outside [0, rows) is filled with -1. */
+int dlm_gather_rows(const int16_t* src_dev, int32_t rows, int32_t n, const int32_t* idx_dev,
+                    int32_t count, int16_t* dst_dev, void* stream);
+
+/* out[i] = (f[i] - mean) / std over the count values (FP64 statistics,
+ * population standard deviation; all zero if std = 0): the scorer's
+ * training targets for one generation. */
+int dlm_standardize(const int32_t* f_dev, int32_t count, float* out_dev, void* stream);
+
+/* pairs_dev int32[pop][2] = (i, j): j uniform over the other members,
+ * j = floor(w0 (pop - 1) / 2^32) + (that value >= i), w0 = word 0 of
+ * Philox(seed; i, gen, 0, 0x80000009). */
+int dlm_random_pairs(int32_t pop, uint64_t seed, uint32_t gen, int32_t* pairs_dev, void* stream);
+
+/* Keep the pop best of parents (indices 0..pop-1) and offspring (indices
+ * pop..2pop-1) by score ascending, ties by index: out_dev int16[pop][n] and
+ * f_out_dev int32[pop] in rank order.  workspace_dev: 24 * pop bytes. */
+int dlm_pop_update(const int16_t* parents_dev, const int32_t* f_parents_dev,
+                   const int16_t* offspring_dev, const int32_t* f_offspring_dev, int32_t pop,
+                   int32_t n, int16_t* out_dev, int32_t* f_out_dev, void* workspace_dev,
+                   void* stream);
+
+/* ------------------------------------------------------------------------
+ * Offspring scorer (Section 2.3): a colour-permutation-invariant regressor
+ * of the post-search score, trained online with Adam on (start colouring,
+ * score after tabu search) pairs, and used by eq. (select_cross) to rank
+ * offspring.  Form: shared per-class MLP over the class indicator vectors V_i,
+ * sum pooling over the k classes, small head:
+ *   h1_i = LReLU(b1 + V_i W1)  [H1]     h2_i = LReLU(b2 + h1_i W2)  [H2]
+ *   z = sum_i h2_i              h3 = LReLU(b3 + z W3)  [H3]
+ *   y = h3 . w4 + b4            LReLU(x) = max(0.2 x, x)
+ * Only (H1, H2, H3) = (256, 128, 64) is built.  Layer 1 is a gather of W1
+ * rows (equal to the indicator product); layer 2 and its backward products
+ * use BF16 MFMA with FP32 accumulation; FP32 master weights and Adam state,
+ * BF16 working copies of W1 and W2.  All reductions run in a fixed order,
+ * so results are deterministic.
+ *
+ * params_host: FP32, packed W1 [n][H1], b1 [H1], W2 [H1][H2], b2 [H2],
+ * W3 [H2][H3], b3 [H3], w4 [H3], b4 [1] (row-major); copied at creation.
+ * max_batch bounds the batch of dlm_scorer_train / dlm_scorer_grad (the
+ * scorer allocates its training activations for that size).  k <= 256.
+ * ---------------------------------------------------------------------- */
+typedef struct dlm_scorer dlm_scorer; /* opaque: weights, Adam state, workspace */
+
+int dlm_scorer_create(int32_t n, int32_t k, int32_t h1, int32_t h2, int32_t h3, int32_t max_batch,
+                      const float* params_host, dlm_scorer** out);
+int dlm_scorer_destroy(dlm_scorer* s);
+/* number of FP32 parameters (the packed layout above) */
+int dlm_scorer_num_params(const dlm_scorer* s, int64_t* count);
+/* copy the FP32 master parameters (packed layout) to params_dev */
+int dlm_scorer_get_params(const dlm_scorer* s, float* params_dev, void* stream);
+
+/*
+ * Predict the post-search score of `count` colourings.
+ *   colors_dev int16[count][n], colours in [0, k)
+ *   scores_dev float[count] output
+ * Not safe to run concurrently with dlm_scorer_train on the same scorer.
+ */
+int dlm_score_offspring(const dlm_scorer* s, const int16_t* colors_dev, int32_t count,
+                        float* scores_dev, void* stream);
+
+/*
+ * Gradient of the mean squared error (1/count) sum_b (y_b - t_b)^2 with
+ * respect to the packed parameters (1 <= count <= max_batch), written to
+ * grad_dev (float[num_params], may be NULL); loss_dev (float[1], may be NULL)
+ * receives the loss.  The parameters are not changed.
+ */
+int dlm_scorer_grad(dlm_scorer* s, const int16_t* colors_dev, const float* targets_dev,
+                    int32_t count, float* grad_dev, float* loss_dev, void* stream);
+
+/*
+ * Online training (Section 2.3): `epochs` passes over the `count` pairs in
+ * consecutive mini-batches of `batch` (the last may be smaller); each
+ * mini-batch is one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction counted over the scorer's lifetime) on the FP32 master weights,
+ * followed by a BF16 re-cast.  loss_dev (float[epochs * ceil(count/batch)],
+ * may be NULL) receives each step's loss before its update.
+ */
+int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targets_dev,
+                     int32_t count, int32_t batch, int32_t epochs, float lr, float* loss_dev,
+                     void* stream);
 
 #ifdef __cplusplus
 }

@@ -91,6 +91,7 @@ def lib():
                                         C.c_uint32, C.c_uint64, P]
             L.orc_select.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                      C.c_uint32, P]
+            L.orc_random_pairs.argtypes = [C.c_int32, C.c_uint64, C.c_uint32, P]
             _lib = L
     return _lib
 
@@ -250,3 +251,9 @@ def select(scores: np.ndarray, keep: int, mode: int, seed: int = 0, gen: int = 0
     out = np.zeros(max(keep, 1), dtype=np.int32)
     lib().orc_select(_p(s), s.shape[0], keep, mode, seed, gen, _p(out))
     return out[:keep]
+
+
+def random_pairs(pop: int, seed: int, gen: int) -> np.ndarray:
+    out = np.zeros((max(pop, 1), 2), dtype=np.int32)
+    lib().orc_random_pairs(pop, seed, gen, _p(out))
+    return out[:pop]

@@ -716,3 +716,19 @@ void orc_select(const float* scores, int32_t count, int32_t keep, int32_t mode, 
   }
   free(key);
 }
+
+/* ------------------------------------------------------------------ */
+/* Parent pairing of the simplified generation: individual i crosses   */
+/* with a uniform other member j (Philox counter (i, gen, 0, 0x80000009)). */
+/* ------------------------------------------------------------------ */
+void orc_random_pairs(int32_t pop, uint64_t seed, uint32_t gen, int32_t* pairs) {
+  for (int32_t i = 0; i < pop; i++) {
+    int32_t j = 0;
+    if (pop > 1) {
+      j = (int32_t)orc_uniform(word0((uint32_t)i, gen, 0, 0x80000009u, seed), (uint32_t)(pop - 1));
+      if (j >= i) j++;
+    }
+    pairs[2 * i] = i;
+    pairs[2 * i + 1] = j;
+  }
+}

@@ -7,9 +7,15 @@ arguments.  Import fails loudly when the library has not been built.
 from ._abi import (  # noqa: F401
     DlmError,
     Graph,
+    MultiBatch,
     NSTATS,
+    Scorer,
     abi_version,
     evaluate,
+    gather_rows,
+    pop_update,
+    random_pairs,
+    standardize,
     gpx_batch,
     select,
     init_population,

@@ -28,7 +28,11 @@ INIT_MODES = {"random": 0, "greedy": 1}
 EXPORTS = [
     "dlm_abi_version", "dlm_last_error", "dlm_graph_create", "dlm_graph_destroy", "dlm_graph_info",
     "dlm_init_population", "dlm_tabu_batch", "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
-    "dlm_wvcp_batch",
+    "dlm_wvcp_batch", "dlm_scorer_create", "dlm_scorer_destroy", "dlm_scorer_num_params",
+    "dlm_scorer_get_params", "dlm_score_offspring", "dlm_scorer_grad", "dlm_scorer_train",
+    "dlm_gather_rows", "dlm_standardize", "dlm_random_pairs", "dlm_pop_update",
+    "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
+    "dlm_multi_plan_destroy", "dlm_multi_autotune",
 ]
 
 
@@ -66,6 +70,22 @@ def lib():
             L.dlm_gpx_batch.argtypes = [P, I32, P, I32, P, I32, I32, U64, C.c_uint32, P, P]
             L.dlm_select.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P, P]
             L.dlm_wvcp_batch.argtypes = [P, C.c_void_p, I32, P, P, P, P, P]
+            L.dlm_scorer_create.argtypes = [I32, I32, I32, I32, I32, I32, P, C.POINTER(P)]
+            L.dlm_scorer_destroy.argtypes = [P]
+            L.dlm_scorer_num_params.argtypes = [P, C.POINTER(I64)]
+            L.dlm_scorer_get_params.argtypes = [P, P, P]
+            L.dlm_score_offspring.argtypes = [P, P, I32, P, P]
+            L.dlm_scorer_grad.argtypes = [P, P, P, I32, P, P, P]
+            L.dlm_scorer_train.argtypes = [P, P, P, I32, I32, I32, C.c_float, P, P]
+            L.dlm_gather_rows.argtypes = [P, I32, I32, P, I32, P, P]
+            L.dlm_standardize.argtypes = [P, I32, P, P]
+            L.dlm_random_pairs.argtypes = [I32, U64, C.c_uint32, P, P]
+            L.dlm_pop_update.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
+            L.dlm_multi_plan_create.argtypes = [P, I32, P, P, C.POINTER(P)]
+            L.dlm_multi_plan_launch.argtypes = [P, P]
+            L.dlm_multi_plan_info.argtypes = [P] + [C.POINTER(I32)] * 4
+            L.dlm_multi_plan_destroy.argtypes = [P]
+            L.dlm_multi_autotune.argtypes = [P, I32, I32, P, P, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -255,3 +275,211 @@ def wvcp_batch(graph: Graph, colors: torch.Tensor, k: int, iters_per_round: int,
                                 _stream(stream)))
     o["colors"] = colors
     return o
+
+
+SCORER_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3", "w4", "b4")
+
+
+class Scorer:
+    """dlm_scorer: per-class MLP offspring scorer (FP32 master, BF16 working copy, Adam)."""
+
+    def __init__(self, n: int, k: int, params: dict, max_batch: int = 1024,
+                 widths: tuple = (256, 128, 64)):
+        flat = np.concatenate([np.ascontiguousarray(params[nm], dtype=np.float32).reshape(-1)
+                               for nm in SCORER_NAMES])
+        h = C.c_void_p()
+        _check("dlm_scorer_create", lib().dlm_scorer_create(n, k, *widths, max_batch, _ptr(flat),
+                                                            C.byref(h)))
+        self._h, self.n, self.k, self.max_batch = h, n, k, max_batch
+        self.shapes = {nm: np.asarray(params[nm]).shape for nm in SCORER_NAMES}
+        cnt = C.c_int64()
+        _check("dlm_scorer_num_params", lib().dlm_scorer_num_params(h, C.byref(cnt)))
+        self.num_params = cnt.value
+        assert self.num_params == flat.size
+
+    def unpack(self, flat: np.ndarray) -> dict:
+        out, o = {}, 0
+        for nm in SCORER_NAMES:
+            sz = int(np.prod(self.shapes[nm]))
+            out[nm] = flat[o:o + sz].reshape(self.shapes[nm])
+            o += sz
+        return out
+
+    def params(self, stream=None) -> dict:
+        buf = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        _check("dlm_scorer_get_params", lib().dlm_scorer_get_params(self._h, _ptr(buf), _stream(stream)))
+        return self.unpack(buf.cpu().numpy())
+
+    def score(self, colors: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """dlm_score_offspring -> float32 [count]."""
+        _dev(colors, torch.int16, "colors")
+        cnt = colors.shape[0]
+        out = out if out is not None else torch.empty(cnt, dtype=torch.float32, device=colors.device)
+        _check("dlm_score_offspring", lib().dlm_score_offspring(self._h, _ptr(colors), cnt, _ptr(out),
+                                                                _stream(stream)))
+        return out
+
+    def grad(self, colors: torch.Tensor, targets: torch.Tensor, stream=None):
+        """dlm_scorer_grad -> (flat FP32 gradient of the mean squared error, loss)."""
+        _dev(colors, torch.int16, "colors")
+        _dev(targets, torch.float32, "targets")
+        g = torch.empty(self.num_params, dtype=torch.float32, device=colors.device)
+        loss = torch.empty(1, dtype=torch.float32, device=colors.device)
+        _check("dlm_scorer_grad", lib().dlm_scorer_grad(self._h, _ptr(colors), _ptr(targets),
+                                                        colors.shape[0], _ptr(g), _ptr(loss),
+                                                        _stream(stream)))
+        return g, loss
+
+    def train(self, colors: torch.Tensor, targets: torch.Tensor, batch: int, epochs: int,
+              lr: float = 1e-3, stream=None) -> torch.Tensor:
+        """dlm_scorer_train -> per-step losses."""
+        _dev(colors, torch.int16, "colors")
+        _dev(targets, torch.float32, "targets")
+        cnt = colors.shape[0]
+        steps = epochs * ((cnt + batch - 1) // batch)
+        loss = torch.empty(max(steps, 1), dtype=torch.float32, device=colors.device)
+        _check("dlm_scorer_train", lib().dlm_scorer_train(self._h, _ptr(colors), _ptr(targets), cnt,
+                                                          batch, epochs, C.c_float(lr), _ptr(loss),
+                                                          _stream(stream)))
+        return loss[:steps]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dlm_scorer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gather_rows(src: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """dlm_gather_rows -> int16 [len(idx), n]."""
+    _dev(src, torch.int16, "src")
+    _dev(idx, torch.int32, "idx")
+    out = out if out is not None else torch.empty((idx.shape[0], src.shape[1]), dtype=torch.int16,
+                                                  device=src.device)
+    _check("dlm_gather_rows", lib().dlm_gather_rows(_ptr(src), src.shape[0], src.shape[1], _ptr(idx),
+                                                    idx.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def standardize(f: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """dlm_standardize -> float32 (f - mean) / std."""
+    _dev(f, torch.int32, "f")
+    out = out if out is not None else torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
+    _check("dlm_standardize", lib().dlm_standardize(_ptr(f), f.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def random_pairs(pop: int, seed: int, gen: int, out: torch.Tensor | None = None, stream=None):
+    """dlm_random_pairs -> int32 [pop, 2]."""
+    out = out if out is not None else torch.empty((pop, 2), dtype=torch.int32, device="cuda")
+    _check("dlm_random_pairs", lib().dlm_random_pairs(pop, seed & (2**64 - 1), gen & 0xffffffff,
+                                                      _ptr(out), _stream(stream)))
+    return out
+
+
+def pop_update(parents: torch.Tensor, f_parents: torch.Tensor, offspring: torch.Tensor,
+               f_offspring: torch.Tensor, out=None, f_out=None, stream=None):
+    """dlm_pop_update -> (colours [pop, n], scores [pop]) of the best pop of both."""
+    pop, n = parents.shape
+    for t, nm in ((parents, "parents"), (offspring, "offspring")):
+        _dev(t, torch.int16, nm)
+    for t, nm in ((f_parents, "f_parents"), (f_offspring, "f_offspring")):
+        _dev(t, torch.int32, nm)
+    out = out if out is not None else torch.empty_like(parents)
+    f_out = f_out if f_out is not None else torch.empty_like(f_parents)
+    ws = torch.empty(3 * pop, dtype=torch.int64, device=parents.device)
+    _check("dlm_pop_update", lib().dlm_pop_update(_ptr(parents), _ptr(f_parents), _ptr(offspring),
+                                                  _ptr(f_offspring), pop, n, _ptr(out), _ptr(f_out),
+                                                  _ptr(ws), _stream(stream)))
+    return out, f_out
+
+
+class MultiItem(C.Structure):
+    _fields_ = [("g", C.c_void_p), ("k", C.c_int32), ("max_iters", C.c_int32), ("pop", C.c_int32),
+                ("ind_base", C.c_int32), ("ten_num", C.c_int32), ("ten_den", C.c_int32),
+                ("ten_rand", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64),
+                ("colors_dev", C.c_void_p), ("f_best_dev", C.c_void_p), ("iters_dev", C.c_void_p),
+                ("stats_dev", C.c_void_p), ("hash_dev", C.c_void_p)]
+
+
+class MultiConfig(C.Structure):
+    _fields_ = [("block", C.c_int32), ("lds_budget", C.c_int32)]
+
+
+class MultiBatch:
+    """An uneven batch: per graph a population, searched by one persistent hipGraph launch.
+
+    ``jobs`` is a list of dicts with keys graph (Graph), colors (int16 device
+    tensor [pop, n]), k, iters, seed and optionally ind_base, ten_num,
+    ten_den, ten_rand.  Outputs (f_best, iters, stats, hash) are allocated
+    here and refreshed by every ``launch``.
+    """
+
+    def __init__(self, jobs: list, block: int = 0, lds_budget: int = 0, stream=None):
+        self.jobs = jobs
+        self._items = (MultiItem * len(jobs))()
+        for i, j in enumerate(jobs):
+            col = _dev(j["colors"], torch.int16, "colors")
+            pop = col.shape[0]
+            j.setdefault("f_best", torch.empty(pop, dtype=torch.int32, device=col.device))
+            j.setdefault("iters_out", torch.empty(pop, dtype=torch.int32, device=col.device))
+            j.setdefault("stats", torch.empty((pop, NSTATS), dtype=torch.int64, device=col.device))
+            j.setdefault("hash", torch.empty(pop, dtype=torch.int64, device=col.device))
+            self._items[i] = MultiItem(
+                j["graph"].handle.value, j["k"], j["iters"], pop, j.get("ind_base", 0),
+                j.get("ten_num", 6), j.get("ten_den", 10), j.get("ten_rand", 10), 0,
+                j["seed"] & (2**64 - 1), col.data_ptr(), j["f_best"].data_ptr(),
+                j["iters_out"].data_ptr(), j["stats"].data_ptr(), j["hash"].data_ptr())
+        self.config = MultiConfig(block, lds_budget)
+        h = C.c_void_p()
+        _check("dlm_multi_plan_create", lib().dlm_multi_plan_create(self._items, len(jobs),
+                                                                    C.byref(self.config),
+                                                                    _stream(stream), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def autotune(cls, jobs: list, calib_iters: int = 2000, stream=None):
+        """dlm_multi_autotune -> (best (block, lds_budget), rates of all 12 candidates)."""
+        items = (MultiItem * len(jobs))()
+        keep = []
+        for i, j in enumerate(jobs):
+            col = _dev(j["colors"], torch.int16, "colors")
+            pop = col.shape[0]
+            scratch = [torch.empty(pop, dtype=torch.int32, device=col.device) for _ in range(2)]
+            keep.append(scratch)
+            items[i] = MultiItem(j["graph"].handle.value, j["k"], j["iters"], pop, j.get("ind_base", 0),
+                                 j.get("ten_num", 6), j.get("ten_den", 10), j.get("ten_rand", 10), 0,
+                                 j["seed"] & (2**64 - 1), col.data_ptr(), scratch[0].data_ptr(),
+                                 scratch[1].data_ptr(), None, None)
+        best = MultiConfig()
+        rates = np.zeros(12, dtype=np.float32)
+        _check("dlm_multi_autotune", lib().dlm_multi_autotune(items, len(jobs), calib_iters,
+                                                              C.byref(best), _ptr(rates),
+                                                              _stream(stream)))
+        return (best.block, best.lds_budget), rates
+
+    def info(self) -> dict:
+        g, l, ng, t = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check("dlm_multi_plan_info", lib().dlm_multi_plan_info(self._h, C.byref(g), C.byref(l),
+                                                                C.byref(ng), C.byref(t)))
+        return {"grid": g.value, "lds_bytes": l.value, "graphs_on_device_table": ng.value,
+                "items": t.value}
+
+    def launch(self, stream=None):
+        _check("dlm_multi_plan_launch", lib().dlm_multi_plan_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dlm_multi_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

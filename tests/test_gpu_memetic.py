@@ -1,0 +1,77 @@
+"""GPU tests of the memetic generation steps (Algorithm 1, simplified form):
+pairing against the oracle's Philox draw, gather / standardise / (mu+lambda)
+update against numpy definitions, and a short learned and plain loop whose
+reported scores are re-derived from the colourings."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from workloads.graphs import gnp
+from workloads.scorer_init import scorer_weights
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dlm():
+    import paper_2109_05948_amd as dlm
+    return dlm
+
+
+def test_random_pairs(dlm, dev):
+    for pop in (1, 2, 7, 8192):
+        say(f"pairs pop={pop}")
+        got = dlm.random_pairs(pop, seed=11, gen=3).cpu().numpy()
+        assert (got == oracle.random_pairs(pop, 11, 3)).all()
+        if pop > 1:
+            assert (got[:, 0] != got[:, 1]).all()
+
+
+def test_gather_standardize_update(dlm, dev):
+    rng = np.random.default_rng(0)
+    src = rng.integers(0, 9, (50, 33)).astype(np.int16)
+    idx = np.array([3, 49, 0, 3, -1, 50], np.int32)
+    say("gather_rows")
+    got = dlm.gather_rows(torch.from_numpy(src).cuda(), torch.from_numpy(idx).cuda()).cpu().numpy()
+    assert (got[:4] == src[idx[:4]]).all() and (got[4:] == -1).all()
+    f = rng.integers(0, 40, 1000).astype(np.int32)
+    say("standardize")
+    s = dlm.standardize(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert np.allclose(s, (f - f.mean()) / f.std(), rtol=1e-5, atol=1e-6)
+    assert (dlm.standardize(torch.full((5,), 7, dtype=torch.int32, device="cuda")).cpu().numpy() == 0).all()
+    pop, n = 300, 20
+    par = rng.integers(0, 5, (pop, n)).astype(np.int16)
+    off = rng.integers(0, 5, (pop, n)).astype(np.int16)
+    fp = rng.integers(0, 30, pop).astype(np.int32)
+    fo = rng.integers(0, 30, pop).astype(np.int32)
+    say("pop_update")
+    out, fout = dlm.pop_update(*(torch.from_numpy(x).cuda() for x in (par, fp, off, fo)))
+    order = np.argsort(np.concatenate([fp, fo]), kind="stable")[:pop]
+    pool = np.concatenate([par, off])
+    assert (fout.cpu().numpy() == np.concatenate([fp, fo])[order]).all()
+    assert (out.cpu().numpy() == pool[order]).all()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_short_memetic_loop(dlm, dev, learned):
+    from paper_2109_05948_amd import memetic
+    g = gnp(120, 0.5, seed=3)
+    k, pop = 16, 64
+    G = dlm.Graph.from_csr(g)
+    say(f"memetic learned={learned}")
+    res = memetic.run(G, k, pop, 600, learned=learned, seed=1, cutoff_s=60, max_generations=4,
+                      scorer_params=scorer_weights(g.n, seed=0), batch=64, epochs=2)
+    bests = [h[2] for h in res.history]
+    assert all(b2 <= b1 for b1, b2 in zip(bests, bests[1:]))   # the (mu+lambda) update keeps the best
+    assert res.best == bests[-1]
+    assert res.tabu_moves > 0
+    if learned and res.generations:
+        assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()
