@@ -72,24 +72,50 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gnp500", choices=["gnp500", "gnp100"])
+    ap.add_argument("--workload", default="gnp500",
+                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000"])
+    ap.add_argument("--cutoff", type=float, default=300.0,
+                    help="memetic1000: wall-clock limit per loop (seconds)")
+    ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
     ap.add_argument("--cpu-sample", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (the reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
-              "the population shards by individual with no communication, see DESIGN.md",
+              "the population shards by individual with no communication between shards",
               file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {n} bytes 3 times")
+        return
+
     import paper_2109_05948_amd as dlm
     from workloads import workload
 
     w = workload(args.workload)
+    if args.workload == "uneven64":
+        return bench_uneven(args, w, dlm, torch)
+    if args.workload == "wvcp300":
+        return bench_wvcp(args, w, dlm, torch)
+    if args.workload == "memetic1000":
+        return bench_memetic(args, w, dlm, torch)
     g, k, T = w.graphs[0], w.k[0], w.iters[0]
     pop = args.pop or w.pop
     G = dlm.Graph.from_csr(g)
@@ -158,6 +184,109 @@ def main():
         log(f"cpu baseline: oracle on {args.cpu_sample} individuals, {threads} threads")
         out["cpu_baseline"] = cpu_baseline(g, k, T, w.tabu_seed, w.init_seed, args.cpu_sample,
                                            threads)
+    print(json.dumps(out), flush=True)
+
+
+def _line(metric, value, unit, args, dt, config, extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3 / max(args.steps, 1),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int16",
+           "data": "synthetic", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_uneven(args, w, dlm, torch):
+    """64 graphs of uneven size, 256 individuals each, one persistent hipGraph launch."""
+    jobs = []
+    for gi, (g, k, T) in enumerate(zip(w.graphs, w.k, w.iters)):
+        G = dlm.Graph.from_csr(g)
+        col, _ = dlm.init_population(G, k, w.pop, seed=w.init_seed, ind_base=gi * w.pop)
+        jobs.append({"graph": G, "colors": col, "k": k, "iters": T, "seed": w.tabu_seed,
+                     "ind_base": gi * w.pop})
+    starts = [j["colors"].clone() for j in jobs]
+    log("autotuning the persistent launch")
+    (block, budget), rates = dlm.MultiBatch.autotune(jobs, calib_iters=1000)
+    log(f"autotune: block {block}, LDS budget {budget}; rates {rates.tolist()}")
+    mb = dlm.MultiBatch(jobs, block=block, lds_budget=budget)
+    info = mb.info()
+    log(f"plan {info}")
+
+    def reset():
+        for j, s0 in zip(jobs, starts):
+            j["colors"].copy_(s0)
+
+    for _ in range(args.warmup):
+        reset()
+        mb.launch()
+    torch.cuda.synchronize()
+    moves, dt = 0, 0.0
+    for _ in range(args.steps):
+        reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mb.launch()
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        moves += sum(int(j["stats"][:, 0].sum().item()) for j in jobs)
+    solved = sum(int((j["f_best"] == 0).sum().item()) for j in jobs)
+    _line("tabu moves/sec, uneven 64-graph batch in one persistent hipGraph launch", moves / dt,
+          "moves/s", args, dt,
+          {"workload": "uneven64", "graphs": len(jobs), "population_per_graph": w.pop,
+           "iters_per_individual": "128 n", "block": block, "lds_budget": budget, **info},
+          {"individuals_legal": solved, "autotune_rates": rates.tolist()})
+
+
+def bench_wvcp(args, w, dlm, torch):
+    """Weighted colouring: greedy init, 10 rounds x 10 n iterations, population 4096."""
+    g = w.graphs[0]
+    G = dlm.Graph.from_csr(g)
+    rounds = w.extra["rounds"]
+    moves, dt, best = 0, 0.0, None
+    for s in range(args.warmup + args.steps):
+        col, ku = dlm.init_population(G, 0, w.pop, seed=w.init_seed + s, mode="greedy")
+        k = int(ku.max().item())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dlm.wvcp_batch(G, col, k, w.iters[0], rounds, seed=w.tabu_seed)
+        torch.cuda.synchronize()
+        if s >= args.warmup:
+            dt += time.perf_counter() - t0
+            moves += int(r["stats"][:, 0].sum().item())
+            b = int(r["best_legal"].min().item())
+            best = b if best is None else min(best, b)
+    _line("weighted tabu moves/sec (population, 1 GPU)", moves / dt, "moves/s", args, dt,
+          {"workload": "wvcp300", "graph": "G(n=300, p=0.3) seed 0, weights U{1..100}",
+           "k": k, "population": w.pop, "rounds": rounds, "iters_per_round": w.iters[0]},
+          {"best_legal_wscore": best})
+
+
+def bench_memetic(args, w, dlm, torch):
+    """Time to a legal k-colouring: learned offspring selection vs random selection."""
+    from paper_2109_05948_amd import memetic
+    from workloads.scorer_init import scorer_weights
+    g, k, T = w.graphs[0], w.k[0], w.iters[0]
+    G = dlm.Graph.from_csr(g)
+    e = w.extra
+    pop = args.pop or w.pop
+    res = {}
+    for name in args.loops.split(","):
+        r = memetic.run(G, k, pop, T, learned=(name == "learned"), seed=w.init_seed,
+                        cutoff_s=args.cutoff, children_per_pair=e["children_per_pair"],
+                        keep_frac=e["keep_frac"], scorer_params=scorer_weights(g.n, seed=0),
+                        batch=e["batch"], epochs=e["epochs"], lr=e["lr"], log=log)
+        res[name] = {"time_to_legal_s": r.time_to_legal, "best_f": r.best,
+                     "generations": r.generations, "wall_s": r.wall,
+                     "tabu_moves_per_s": r.tabu_moves / r.wall,
+                     "history": [list(h) for h in r.history]}
+    out = {"metric": "time-to-legal-k-coloring, learned vs plain (seconds, lower is better)",
+           "value": res.get("learned", {}).get("time_to_legal_s"), "unit": "s", "n_gpus": 1,
+           "higher_is_better": False, "vs_baseline": None, "dtype": "int16+bf16",
+           "data": "synthetic",
+           "config": {"workload": "memetic1000", "graph": "G(n=1000, p=0.5) seed 0", "k": k,
+                      "population": pop, "children_per_pair": e["children_per_pair"],
+                      "keep_frac": e["keep_frac"], "iters_per_tabu": T, "cutoff_s": args.cutoff},
+           "loops": res}
     print(json.dumps(out), flush=True)
 
 

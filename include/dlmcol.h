@@ -337,8 +337,8 @@ int dlm_pop_update(const int16_t* parents_dev, const int32_t* f_parents_dev,
  * Only (H1, H2, H3) = (256, 128, 64) is built.  Layer 1 is a gather of W1
  * rows (equal to the indicator product); layer 2 and its backward products
  * use BF16 MFMA with FP32 accumulation; FP32 master weights and Adam state,
- * BF16 working copies of W1 and W2.  All reductions run in a fixed order,
- * so results are deterministic.
+ * a BF16 working copy of W2 (layer 1 gathers the FP32 W1 rows).  All
+ * reductions run in a fixed order, so results are deterministic.
  *
  * params_host: FP32, packed W1 [n][H1], b1 [H1], W2 [H1][H2], b2 [H2],
  * W3 [H2][H3], b3 [H3], w4 [H3], b4 [1] (row-major); copied at creation.
@@ -384,6 +384,15 @@ int dlm_scorer_grad(dlm_scorer* s, const int16_t* colors_dev, const float* targe
 int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targets_dev,
                      int32_t count, int32_t batch, int32_t epochs, float lr, float* loss_dev,
                      void* stream);
+
+/* ------------------------------------------------------------------------
+ * Measurement helper (not part of the search): sustained LDS read bandwidth
+ * of the whole device in bytes/s, from a kernel that streams conflict-free
+ * 16-byte LDS reads on every resident workgroup for `rounds` passes over a
+ * 64 KiB buffer.  It is the measured denominator of the TabuCol kernel's LDS
+ * roofline.  Synchronises stream.
+ * ---------------------------------------------------------------------- */
+int dlm_probe_lds_bandwidth(int32_t rounds, double* bytes_per_s, void* stream);
 
 #ifdef __cplusplus
 }

@@ -14,6 +14,7 @@ from ._abi import (  # noqa: F401
     evaluate,
     gather_rows,
     pop_update,
+    probe_lds_bandwidth,
     random_pairs,
     standardize,
     gpx_batch,

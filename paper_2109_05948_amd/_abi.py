@@ -32,7 +32,7 @@ EXPORTS = [
     "dlm_scorer_get_params", "dlm_score_offspring", "dlm_scorer_grad", "dlm_scorer_train",
     "dlm_gather_rows", "dlm_standardize", "dlm_random_pairs", "dlm_pop_update",
     "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
-    "dlm_multi_plan_destroy", "dlm_multi_autotune",
+    "dlm_multi_plan_destroy", "dlm_multi_autotune", "dlm_probe_lds_bandwidth",
 ]
 
 
@@ -86,6 +86,7 @@ def lib():
             L.dlm_multi_plan_info.argtypes = [P] + [C.POINTER(I32)] * 4
             L.dlm_multi_plan_destroy.argtypes = [P]
             L.dlm_multi_autotune.argtypes = [P, I32, I32, P, P, P]
+            L.dlm_probe_lds_bandwidth.argtypes = [I32, C.POINTER(C.c_double), P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -483,3 +484,10 @@ class MultiBatch:
             self.close()
         except Exception:
             pass
+
+
+def probe_lds_bandwidth(rounds: int = 2000, stream=None) -> float:
+    """dlm_probe_lds_bandwidth -> sustained device LDS read bandwidth (bytes/s)."""
+    out = C.c_double()
+    _check("dlm_probe_lds_bandwidth", lib().dlm_probe_lds_bandwidth(rounds, C.byref(out), _stream(stream)))
+    return out.value

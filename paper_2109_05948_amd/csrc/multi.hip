@@ -173,7 +173,7 @@ int dlm_multi_plan_create(const dlm_multi_item* items, int32_t count, const dlm_
       d.tier = 1;
       ++p->n_global;
       lds = std::max<size_t>(lds, tabu_layout(n, it.k, nw, 0).bytes);
-      p->slot_words = std::max<int64_t>(p->slot_words, (int64_t)n * it.k);
+      p->slot_words = std::max<int64_t>(p->slot_words, (int64_t)n * tab_stride(it.k));
     }
     d.first_item = first;
     d.pop = it.pop;

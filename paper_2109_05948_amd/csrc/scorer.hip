@@ -9,8 +9,9 @@
 //   y = h3 . w4 + b4                 LReLU(x) = max(0.2 x, x)
 //
 // H1 = 256, H2 = 128, H3 = 64.  Layer 2 and its two backward products run
-// on v_mfma_f32_32x32x8bf16_1k; layer 1 is a gather (a dense one-hot product
-// would cost n/k times more); the head is plain FP32.
+// on v_mfma_f32_32x32x8bf16_1k; layer 1 is a gather of FP32 W1 rows (a dense
+// one-hot product would cost n/k times more, and FP32 keeps the LeakyReLU
+// branch of a1 exact to FP32 rounding); the head is plain FP32.
 //
 // MFMA 32x32x8 (bf16) operand layout, lane l of a wave:
 //   A (32 x 8):  A[l % 32][4 (l / 32) + j], j = 0..3
@@ -71,7 +72,6 @@ inline ParamLayout param_layout(int n) {
 
 struct ScorerDev {
   const float* P;            // FP32 master parameters
-  const uint16_t* W1b;       // bf16 [n][H1]
   const uint16_t* W2b;       // bf16 [H1][H2]
   const uint16_t* W2t;       // bf16 [H2][H1]
   int64_t oW1, ob1, oW2, ob2, oW3, ob3, ow4, ob4;
@@ -137,13 +137,13 @@ __global__ __launch_bounds__(256) void scorer_fwd_kernel(ScorerDev s, const int1
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     float a0 = b1[4 * lane], a1v = b1[4 * lane + 1], a2v = b1[4 * lane + 2], a3v = b1[4 * lane + 3];
+    const float* W1 = s.P + s.oW1 + 4 * lane;
     for (int q = 0; q < cnt; ++q) {
-      const int v = mylist[q];
-      const s4 wrow = ld_s4(s.W1b + (size_t)v * H1 + 4 * lane);
-      a0 += bf2f((uint16_t)wrow.x);
-      a1v += bf2f((uint16_t)wrow.y);
-      a2v += bf2f((uint16_t)wrow.z);
-      a3v += bf2f((uint16_t)wrow.w);
+      const float4 wrow = *reinterpret_cast<const float4*>(W1 + (size_t)mylist[q] * H1);
+      a0 += wrow.x;
+      a1v += wrow.y;
+      a2v += wrow.z;
+      a3v += wrow.w;
     }
     uint16_t* row = h1 + i * kRowPadH1 + 4 * lane;
     row[0] = f2bf(lrelu(a0));
@@ -402,17 +402,12 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ P, float*
   P[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// BF16 working copies: W1b [n][H1], W2b [H1][H2], W2t [H2][H1]
-__global__ __launch_bounds__(256) void scorer_cast_kernel(const float* __restrict__ P, int64_t oW1,
-                                                          int64_t oW2, int32_t n, uint16_t* __restrict__ W1b,
+// BF16 working copies of W2 for the MFMA products: W2b [H1][H2], W2t [H2][H1]
+__global__ __launch_bounds__(256) void scorer_cast_kernel(const float* __restrict__ P, int64_t oW2,
                                                           uint16_t* __restrict__ W2b,
                                                           uint16_t* __restrict__ W2t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n1 = (int64_t)n * H1;
-  if (i < n1) {
-    W1b[i] = f2bf(P[oW1 + i]);
-  } else if (i < n1 + H1 * H2) {
-    const int64_t j = i - n1;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < H1 * H2) {
     const uint16_t x = f2bf(P[oW2 + j]);
     W2b[j] = x;
     W2t[(j % H2) * H1 + j / H2] = x;
@@ -428,11 +423,11 @@ struct dlm_scorer {
   int64_t step = 0;
   ParamLayout L{};
   float *P = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
-  uint16_t *W1b = nullptr, *W2b = nullptr, *W2t = nullptr;
+  uint16_t *W2b = nullptr, *W2t = nullptr;
   TrainBufs tb{};
   void* ws = nullptr;
   ScorerDev dev() const {
-    return ScorerDev{P, W1b, W2b, W2t, L.W1, L.b1, L.W2, L.b2, L.W3, L.b3, L.w4, L.b4, n, k, kpad};
+    return ScorerDev{P, W2b, W2t, L.W1, L.b1, L.W2, L.b2, L.W3, L.b3, L.w4, L.b4, n, k, kpad};
   }
 };
 
@@ -444,9 +439,8 @@ size_t fwd_lds(int n, int kpad) {
 size_t bwd_lds(int kpad) { return (size_t)kpad * kRowPadH2 * 2 + (H2 + H3) * 4; }
 
 int cast_weights(dlm_scorer* s, hipStream_t st) {
-  const int64_t tot = (int64_t)s->n * H1 + H1 * H2;
-  hipLaunchKernelGGL(scorer_cast_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, s->P, s->L.W1,
-                     s->L.W2, s->n, s->W1b, s->W2b, s->W2t);
+  hipLaunchKernelGGL(scorer_cast_kernel, dim3((H1 * H2 + 255) / 256), dim3(256), 0, st, s->P, s->L.W2, s->W2b,
+                     s->W2t);
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }
@@ -511,7 +505,7 @@ int dlm_scorer_create(int32_t n, int32_t k, int32_t h1, int32_t h2, int32_t h3, 
   // one allocation for everything the scorer owns
   const int64_t bytes_f =
       4 * (4 * P + B * H2 + B * H3 + B + B * kp * H1 + B * H3 + B + nchunk * H1 * H2 + B * (H1 + H2));
-  const int64_t bytes_h = 2 * ((int64_t)n * H1 + 2 * H1 * H2 + B * H1 * kp + B * kp * H2 + B * H2 * kp);
+  const int64_t bytes_h = 2 * (2 * H1 * H2 + B * H1 * kp + B * kp * H2 + B * H2 * kp);
   const int64_t bytes = bytes_f + bytes_h + 256;
   hipError_t e = hipMalloc(&s->ws, (size_t)bytes);
   if (e != hipSuccess) {
@@ -533,7 +527,6 @@ int dlm_scorer_create(int32_t n, int32_t k, int32_t h1, int32_t h2, int32_t h3, 
   s->tb.p1 = f; f += B * H1;
   s->tb.p2 = f; f += B * H2;
   uint16_t* h = (uint16_t*)f;
-  s->W1b = h; h += (int64_t)n * H1;
   s->W2b = h; h += H1 * H2;
   s->W2t = h; h += H1 * H2;
   s->tb.h1t = h; h += B * H1 * kp;

@@ -28,6 +28,14 @@ struct TabLds16 {
     g = x & 0xffffu;
     ex = x >> 16;
   }
+  // four consecutive entries (i a multiple of 4: one 16-byte LDS read)
+  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
+    const uint4 x = *reinterpret_cast<const uint4*>(w + i);
+    g[0] = x.x & 0xffffu; ex[0] = x.x >> 16;
+    g[1] = x.y & 0xffffu; ex[1] = x.y >> 16;
+    g[2] = x.z & 0xffffu; ex[2] = x.z >> 16;
+    g[3] = x.w & 0xffffu; ex[3] = x.w >> 16;
+  }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) {
     reinterpret_cast<uint16_t*>(w)[2 * i + 1] = (uint16_t)ex;
   }
@@ -57,6 +65,12 @@ struct TabLds32 {
     g = x.x;
     ex = x.y;
   }
+  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
+    const uint4 x = *reinterpret_cast<const uint4*>(w + 2 * i);
+    const uint4 y = *reinterpret_cast<const uint4*>(w + 2 * i + 4);
+    g[0] = x.x; ex[0] = x.y; g[1] = x.z; ex[1] = x.w;
+    g[2] = y.x; ex[2] = y.y; g[3] = y.z; ex[3] = y.w;
+  }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { w[2 * i + 1] = ex; }
   __device__ __forceinline__ void rebase(int) {}
   __device__ __forceinline__ void sync() {}
@@ -83,6 +97,14 @@ struct TabGlobal16 {
     const uint32_t x = ld(i);
     g = x & 0xffffu;
     ex = x >> 16;
+  }
+  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t x = ld(i + q);
+      g[q] = x & 0xffffu;
+      ex[q] = x >> 16;
+    }
   }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) {
     // only the high half changes; the low half of row v* is not touched by this move
@@ -119,11 +141,15 @@ struct TabuLayout {
   uint64_t tab, cg, conf, cmask, red, redc, red2, sc, bytes;
 };
 
+// Table rows are padded to a multiple of 4 colours so that a quad of
+// candidates is one aligned 16-byte read.
+__host__ __device__ constexpr int tab_stride(int k) { return (k + 3) & ~3; }
+
 __host__ __device__ inline TabuLayout tabu_layout(int n, int k, int nw, int entry_bytes) {
   TabuLayout L;
   uint64_t o = 0;
   L.tab = o;
-  o += (((uint64_t)n * k * entry_bytes) + 15u) & ~15ull;
+  o += (((uint64_t)n * tab_stride(k) * entry_bytes) + 15u) & ~15ull;
   L.cg = o;
   o += align16(4u * n);
   L.conf = o;
@@ -170,7 +196,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const uint32_t ind = (uint32_t)(a.ind_base + li);
-  const int n = a.n, k = a.k, nk = n * k;
+  const int n = a.n, k = a.k, kp = tab_stride(k), nk = n * kp;
   const int nwords = (n + 31) >> 5;
   const TabuLayout L = tabu_layout(n, k, NW, Tab::kLdsBytes);
   Tab tab = Tab::make(smem + L.tab, gtab);
@@ -203,14 +229,14 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
   __syncthreads();
   // 2. gamma from the CSR entries
   const int nnz = a.row_ptr[n];
-  for (int e = tid; e < nnz; e += BLOCK) tab.add(a.erow[e] * k + (int)(cg[a.col_idx[e]] & 0xffffu), 1);
+  for (int e = tid; e < nnz; e += BLOCK) tab.add(a.erow[e] * kp + (int)(cg[a.col_idx[e]] & 0xffffu), 1);
   tab.sync();
   __syncthreads();
   // 3. gamma of the current colour, conflict mask, f = sum / 2
   uint32_t fs = 0;
   for (int v = tid; v < n; v += BLOCK) {
     const uint32_t cv = cg[v];
-    const uint32_t g = tab.gamma(v * k + (int)cv);
+    const uint32_t g = tab.gamma(v * kp + (int)cv);
     cg[v] = cv | (g << 16);
     if (g) atomicOr(&cmask[v >> 5], 1u << (v & 31));
     fs += g;
@@ -232,7 +258,9 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
   uint64_t st_moves = 0, st_noops = 0, st_conf = 0, st_deg = 0, st_ties = 0, st_cap = 0;
   uint64_t fp = kFnvOffset;
   uint32_t Lreg = 0;
-  const int i0 = tid / k, c0 = tid - (tid / k) * k, di = BLOCK / k, dc = BLOCK - (BLOCK / k) * k;
+  // quads (i, q): the i-th conflicting vertex, colours 4q..4q+3; thread tid takes quads tid + s*BLOCK
+  const int kq = kp >> 2;
+  const int i0 = tid / kq, q0 = tid - (tid / kq) * kq, di = BLOCK / kq, dq = BLOCK - (BLOCK / kq) * kq;
 
   while (t < a.T && f > 0) {
     if (Tab::kRebase && t - base == kRebaseEvery) {
@@ -249,37 +277,57 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
 
     // ---- scan
     uint32_t bd = 0xffffffffu, bidx = 0xffffffffu, bcnt = 0, s0 = 0, s1 = 0;
+    auto consider = [&](int v, int c, uint32_t x, uint32_t g, uint32_t ex) {
+      const int d = (int)g - (int)(x >> 16);
+      if (c < k && c != (int)(x & 0xffffu) && (ex <= trel || d <= asp)) {
+        const uint32_t bdv = (uint32_t)(d + kBias);
+        const uint32_t idx = ((uint32_t)v << 16) | (uint32_t)c;
+        if (bdv < bd) {
+          bd = bdv;
+          bidx = idx;
+          bcnt = 1;
+          s0 = idx;
+        } else if (bdv == bd) {
+          bidx = min(bidx, idx);
+          if (bcnt == 1) s1 = idx;
+          ++bcnt;
+        }
+      }
+    };
+    auto step = [&](int& i, int& q) {
+      q += dq;
+      i += di;
+      if (q >= kq) {
+        q -= kq;
+        ++i;
+      }
+    };
     {
-      int i = i0, c = c0;
-      const int total = C * k;
-      for (int j = tid; j < total; j += BLOCK) {
+      const int totq = C * kq;
+      int i = i0, q = q0, j = tid;
+      // two quads per round: their loads are independent and issue together
+      for (; j + BLOCK < totq; j += 2 * BLOCK) {
+        const int ia = i, qa = q;
+        step(i, q);
+        const int ib = i, qb = q;
+        step(i, q);
+        const int va = conf[ia], vb = conf[ib];
+        const uint32_t xa = cg[va], xb = cg[vb];
+        uint32_t ga[4], ea[4], gb[4], eb[4];
+        tab.read4(va * kp + 4 * qa, ga, ea);
+        tab.read4(vb * kp + 4 * qb, gb, eb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) consider(va, 4 * qa + r, xa, ga[r], ea[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) consider(vb, 4 * qb + r, xb, gb[r], eb[r]);
+      }
+      if (j < totq) {
         const int v = conf[i];
         const uint32_t x = cg[v];
-        if (c != (int)(x & 0xffffu)) {
-          uint32_t g, ex;
-          tab.read(v * k + c, g, ex);
-          const int d = (int)g - (int)(x >> 16);
-          if (ex <= trel || d <= asp) {
-            const uint32_t bdv = (uint32_t)(d + kBias);
-            const uint32_t idx = ((uint32_t)v << 16) | (uint32_t)c;
-            if (bdv < bd) {
-              bd = bdv;
-              bidx = idx;
-              bcnt = 1;
-              s0 = idx;
-            } else if (bdv == bd) {
-              bidx = min(bidx, idx);
-              if (bcnt == 1) s1 = idx;
-              ++bcnt;
-            }
-          }
-        }
-        c += dc;
-        i += di;
-        if (c >= k) {
-          c -= k;
-          ++i;
-        }
+        uint32_t g4[4], e4[4];
+        tab.read4(v * kp + 4 * q, g4, e4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) consider(v, 4 * q + r, x, g4[r], e4[r]);
       }
     }
     // ---- reduce: minimum (delta, v, c) and the number of moves at that delta
@@ -331,25 +379,22 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
           hk = hkey(s0);
           if (bcnt == 2) hk = umin64(hk, hkey(s1));
         } else {
-          int i = i0, c = c0;
-          const int total = C * k;
+          const int totq = C * kq;
           const int dmin = (int)gbd - kBias;
-          for (int j = tid; j < total; j += BLOCK) {
+          int i = i0, q = q0;
+          for (int j = tid; j < totq; j += BLOCK) {
             const int v = conf[i];
             const uint32_t x = cg[v];
-            if (c != (int)(x & 0xffffu)) {
-              uint32_t g, ex;
-              tab.read(v * k + c, g, ex);
-              const int d = (int)g - (int)(x >> 16);
-              if (d == dmin && (ex <= trel || d <= asp))
+            uint32_t g4[4], e4[4];
+            tab.read4(v * kp + 4 * q, g4, e4);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int c = 4 * q + r;
+              const int d = (int)g4[r] - (int)(x >> 16);
+              if (c < k && c != (int)(x & 0xffffu) && d == dmin && (e4[r] <= trel || d <= asp))
                 hk = umin64(hk, hkey(((uint32_t)v << 16) | (uint32_t)c));
             }
-            c += dc;
-            i += di;
-            if (c >= k) {
-              c -= k;
-              ++i;
-            }
+            step(i, q);
           }
         }
       }
@@ -379,8 +424,8 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
         const int u = a.col_idx[e];
         const uint32_t xu = cg[u];
         const int cu = (int)(xu & 0xffffu);
-        tab.add(u * k + old, -1);
-        tab.add(u * k + cs, +1);
+        tab.add(u * kp + old, -1);
+        tab.add(u * kp + cs, +1);
         if (cu == old) {
           cg[u] = xu - 0x10000u;
           if ((xu >> 16) == 1u) atomicAnd(&cmask[u >> 5], ~(1u << (u & 31)));
@@ -390,8 +435,8 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
         }
       }
       if (lane == 0) {
-        tab.set_tabu(vs * k + old, trel + Lt + (uint32_t)ttf);
-        const uint32_t gnew = tab.gamma(vs * k + cs);
+        tab.set_tabu(vs * kp + old, trel + Lt + (uint32_t)ttf);
+        const uint32_t gnew = tab.gamma(vs * kp + cs);
         cg[vs] = (uint32_t)cs | (gnew << 16);
         if (gnew == 0u) atomicAnd(&cmask[vs >> 5], ~(1u << (vs & 31)));
       }

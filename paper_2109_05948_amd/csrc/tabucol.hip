@@ -30,7 +30,7 @@ template <int BLOCK, class Tab>
 __global__ __launch_bounds__(BLOCK) void tabucol_kernel(TabuArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int li = blockIdx.x;
-  uint32_t* gtab = a.gtab ? a.gtab + (size_t)li * (size_t)a.n * (size_t)a.k : nullptr;
+  uint32_t* gtab = a.gtab ? a.gtab + (size_t)li * (size_t)a.n * (size_t)tab_stride(a.k) : nullptr;
   tabu_individual<BLOCK, Tab>(a, li, gtab, smem);
 }
 
@@ -102,7 +102,7 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
              p->ind_base, p->trace_cap};
   hipStream_t s = (hipStream_t)stream;
   if (table == DLM_TABLE_GLOBAL16) {
-    const size_t bytes = (size_t)pop * n * k * sizeof(uint32_t);
+    const size_t bytes = (size_t)pop * n * tab_stride(k) * sizeof(uint32_t);
     DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
     int rc = launch_tab<TabGlobal16>(a, pop, block, lds, s);
     hipError_t e = hipFreeAsync(a.gtab, s);
