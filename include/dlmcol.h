@@ -112,6 +112,7 @@ int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, uint64_t see
 #define DLM_TABLE_LDS16 1      /* 32-bit word per (v,c): gamma 16 bits | tabu 16 bits, LDS */
 #define DLM_TABLE_LDS32 2      /* 64-bit word per (v,c): gamma int32 | tabu expiry, LDS */
 #define DLM_TABLE_GLOBAL16 3   /* packed 16-bit words in device memory (large n*k) */
+#define DLM_TABLE_SPLIT16 4    /* gamma 16 bits in LDS, tabu 16 bits in device memory */
 
 typedef struct dlm_tabu_params {
   int32_t k;          /* colours, 1 <= k <= 32767 */
@@ -159,7 +160,8 @@ int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
  * bit-identical results.  Work items (graph, individual) are taken
  * longest-first from an atomic queue by a grid sized to the device's
  * resident capacity; graphs whose table fits the LDS budget use the LDS16
- * table, the others the device-memory table.  A plan captures the queue
+ * table, graphs whose 16-bit gamma alone fits use the split table (expiries
+ * in device memory), the others the device-memory table.  A plan captures the queue
  * reset and the persistent kernel into a hipGraph once; each launch replays
  * it on the caller's stream and searches whatever the item buffers hold.
  * The plan keeps the item pointers: buffers and graphs must outlive it.
@@ -186,7 +188,8 @@ typedef struct dlm_multi_plan dlm_multi_plan;
 int dlm_multi_plan_create(const dlm_multi_item* items, int32_t count, const dlm_multi_config* cfg,
                           void* stream, dlm_multi_plan** out);
 int dlm_multi_plan_launch(dlm_multi_plan* plan, void* stream);
-/* grid size, dynamic LDS bytes, graphs on the device-memory table, items */
+/* grid size, dynamic LDS bytes, graphs using device memory for (part of)
+ * their table, items */
 int dlm_multi_plan_info(const dlm_multi_plan* plan, int32_t* grid, int32_t* lds_bytes,
                         int32_t* n_global, int32_t* total_items);
 int dlm_multi_plan_destroy(dlm_multi_plan* plan);

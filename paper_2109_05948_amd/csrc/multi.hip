@@ -5,8 +5,10 @@
 // n * k * iterations, descending).  The grid holds as many workgroups as the
 // device keeps resident at the launch's LDS size; each workgroup pops items
 // from an atomic counter until the queue is empty, so every workgroup exits.
-// A graph whose table fits the launch's LDS budget runs the LDS16 table;
-// the others run the device-memory table, one slot per workgroup.  The
+// A graph whose table fits the launch's LDS budget runs the LDS16 table, one
+// whose gamma alone fits runs the split table (expiries in device memory),
+// the others the device-memory table; device storage is one slot per
+// workgroup.  The
 // search itself is the same function as dlm_tabu_batch's, so trajectories
 // are identical to single-graph runs with the same seeds and indices.
 #include <algorithm>
@@ -22,7 +24,7 @@ namespace dlm {
 
 struct MultiDesc {
   TabuArgs a;
-  int32_t tier;        // 0 = LDS16, 1 = GLOBAL16
+  int32_t tier;        // 0 = LDS16, 1 = GLOBAL16, 2 = SPLIT16
   int32_t first_item;  // items [first_item, first_item + pop) belong to this graph
   int32_t pop;
   int32_t pad;
@@ -39,7 +41,8 @@ __global__ __launch_bounds__(BLOCK) void tabu_multi_kernel(const MultiDesc* __re
                                                            uint32_t* __restrict__ gslots, int64_t slot_words) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int32_t s_item;
-  uint32_t* gtab = gslots ? gslots + (size_t)blockIdx.x * (size_t)slot_words : nullptr;
+  unsigned char* gtab =
+      gslots ? reinterpret_cast<unsigned char*>(gslots + (size_t)blockIdx.x * (size_t)slot_words) : nullptr;
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(queue, 1u);
@@ -51,6 +54,7 @@ __global__ __launch_bounds__(BLOCK) void tabu_multi_kernel(const MultiDesc* __re
     const MultiDesc& d = descs[g];
     const int li = item - d.first_item;
     if (d.tier == 0) tabu_individual<BLOCK, TabLds16>(d.a, li, nullptr, smem);
+    else if (d.tier == 2) tabu_individual<BLOCK, TabSplit16>(d.a, li, gtab, smem);
     else tabu_individual<BLOCK, TabGlobal16>(d.a, li, gtab, smem);
   }
 }
@@ -166,9 +170,15 @@ int dlm_multi_plan_create(const dlm_multi_item* items, int32_t count, const dlm_
                    it.stats_dev, it.hash_dev, nullptr, nullptr, make_key(it.seed), n, it.k, it.max_iters,
                    it.ten_num, it.ten_den, it.ten_rand, it.ind_base, 0};
     const uint64_t lds16 = tabu_layout(n, it.k, nw, TabLds16::kLdsBytes).bytes;
+    const uint64_t ldss = tabu_layout(n, it.k, nw, TabSplit16::kLdsBytes).bytes;
     if ((int64_t)lds16 <= budget) {
       d.tier = 0;
       lds = std::max<size_t>(lds, lds16);
+    } else if ((int64_t)ldss <= budget) {
+      d.tier = 2;
+      ++p->n_global;
+      lds = std::max<size_t>(lds, ldss);
+      p->slot_words = std::max<int64_t>(p->slot_words, ((int64_t)n * tab_stride(it.k) * 2 + 3) / 4);
     } else {
       d.tier = 1;
       ++p->n_global;

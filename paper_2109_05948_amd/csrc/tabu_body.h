@@ -17,7 +17,8 @@ struct TabLds16 {
   static constexpr bool kRebase = true;
   static constexpr int kLdsBytes = 4;
   uint32_t* w;
-  __device__ static TabLds16 make(unsigned char* lds, uint32_t*) {
+  static constexpr int kGlobalBytes = 0;
+  __device__ static TabLds16 make(unsigned char* lds, unsigned char*) {
     return TabLds16{reinterpret_cast<uint32_t*>(lds)};
   }
   __device__ __forceinline__ void zero(int i) { w[i] = 0u; }
@@ -51,7 +52,8 @@ struct TabLds32 {
   static constexpr bool kRebase = false;
   static constexpr int kLdsBytes = 8;
   uint32_t* w;  // w[2i] = gamma, w[2i+1] = absolute expiry
-  __device__ static TabLds32 make(unsigned char* lds, uint32_t*) {
+  static constexpr int kGlobalBytes = 0;
+  __device__ static TabLds32 make(unsigned char* lds, unsigned char*) {
     return TabLds32{reinterpret_cast<uint32_t*>(lds)};
   }
   __device__ __forceinline__ void zero(int i) {
@@ -82,7 +84,10 @@ struct TabGlobal16 {
   static constexpr bool kRebase = true;
   static constexpr int kLdsBytes = 0;
   uint32_t* w;
-  __device__ static TabGlobal16 make(unsigned char*, uint32_t* g) { return TabGlobal16{g}; }
+  static constexpr int kGlobalBytes = 4;
+  __device__ static TabGlobal16 make(unsigned char*, unsigned char* g) {
+    return TabGlobal16{reinterpret_cast<uint32_t*>(g)};
+  }
   __device__ __forceinline__ uint32_t ld(int i) const {
     return __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -121,6 +126,51 @@ struct TabGlobal16 {
   __device__ __forceinline__ void sync() { __threadfence(); }
 };
 
+// Split storage: gamma (16 bits) in LDS, tabu expiries (16 bits, relative
+// to the rebased origin) in device memory.  Half the LDS of LDS16, so twice
+// as many individuals fit on a CU; the expiry rows of the resident
+// individuals stay in L2.  Expiries are read with device-coherent loads.
+struct TabSplit16 {
+  static constexpr bool kRebase = true;
+  static constexpr int kLdsBytes = 2;
+  static constexpr int kGlobalBytes = 2;
+  uint16_t* g;   // LDS gamma
+  uint16_t* tb;  // device tabu expiries
+  __device__ static TabSplit16 make(unsigned char* lds, unsigned char* gm) {
+    return TabSplit16{reinterpret_cast<uint16_t*>(lds), reinterpret_cast<uint16_t*>(gm)};
+  }
+  __device__ __forceinline__ void zero(int i) {
+    g[i] = 0;
+    tb[i] = 0;
+  }
+  __device__ __forceinline__ void add(int i, int d) {
+    // 16-bit add inside the containing 32-bit LDS word; a decrement only
+    // happens on a positive count, so no borrow crosses the halves
+    const uint32_t inc = d > 0 ? 1u : 0xffffu;
+    atomicAdd(reinterpret_cast<uint32_t*>(g) + (i >> 1), (i & 1) ? (inc << 16) : (d > 0 ? 1u : 0xffffffffu));
+  }
+  __device__ __forceinline__ uint32_t gamma(int i) const { return g[i]; }
+  __device__ __forceinline__ uint32_t ldt(int i) const {
+    const uint32_t w = __hip_atomic_load(reinterpret_cast<const uint32_t*>(tb) + (i >> 1), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return (i & 1) ? (w >> 16) : (w & 0xffffu);
+  }
+  __device__ __forceinline__ void read4(int i, uint32_t gg[4], uint32_t ex[4]) const {
+    const uint2 x = *reinterpret_cast<const uint2*>(g + i);
+    const uint64_t t = __hip_atomic_load(reinterpret_cast<const uint64_t*>(tb + i), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    gg[0] = x.x & 0xffffu; gg[1] = x.x >> 16; gg[2] = x.y & 0xffffu; gg[3] = x.y >> 16;
+    ex[0] = (uint32_t)t & 0xffffu; ex[1] = (uint32_t)(t >> 16) & 0xffffu;
+    ex[2] = (uint32_t)(t >> 32) & 0xffffu; ex[3] = (uint32_t)(t >> 48);
+  }
+  __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { tb[i] = (uint16_t)ex; }
+  __device__ __forceinline__ void rebase(int i) {
+    const uint32_t e = ldt(i);
+    tb[i] = (uint16_t)(e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u);
+  }
+  __device__ __forceinline__ void sync() { __threadfence(); }
+};
+
 // ---------------------------------------------------------------------------
 struct TabuArgs {
   const int32_t* row_ptr;
@@ -132,13 +182,13 @@ struct TabuArgs {
   int64_t* stats;
   uint64_t* hash;
   int32_t* trace;
-  uint32_t* gtab;
+  unsigned char* gtab;  // device-memory table storage (global and split tiers)
   Key key;
   int32_t n, k, T, ten_num, ten_den, ten_rand, ind_base, trace_cap;
 };
 
 struct TabuLayout {
-  uint64_t tab, cg, conf, cmask, red, redc, red2, sc, bytes;
+  uint64_t tab, cg, conf, cmask, rp, red, redc, red2, sc, bytes;
 };
 
 // Table rows are padded to a multiple of 4 colours so that a quad of
@@ -156,6 +206,8 @@ __host__ __device__ inline TabuLayout tabu_layout(int n, int k, int nw, int entr
   o += align16(2u * n);
   L.cmask = o;
   o += align16(4u * ((n + 31) / 32));
+  L.rp = o;
+  o += align16(4u * (n + 1));
   L.red = o;
   o += 16u * nw;
   L.redc = o;
@@ -189,9 +241,9 @@ __device__ __forceinline__ void build_conflict_list(const uint32_t* cmask, uint1
 }
 
 // One individual (row li of a.colors) searched by the calling workgroup.
-// gtab: the device-memory table of this workgroup (global tier only).
+// gtab: the device-memory part of this workgroup's table (global and split tiers).
 template <int BLOCK, class Tab>
-__device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint32_t* gtab,
+__device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsigned char* gtab,
                                                 unsigned char* smem) {
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
@@ -207,6 +259,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
   uint32_t* redc = reinterpret_cast<uint32_t*>(smem + L.redc);
   uint64_t* red2 = reinterpret_cast<uint64_t*>(smem + L.red2);
   int32_t* sc = reinterpret_cast<int32_t*>(smem + L.sc);
+  int32_t* rp = reinterpret_cast<int32_t*>(smem + L.rp);  // CSR row offsets, cached
   int16_t* gcol = a.colors + (size_t)li * n;
 
   // 1. start colouring (rejected whole if a colour is outside [0, k)), empty table and mask
@@ -225,6 +278,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
   }
   for (int i = tid; i < nk; i += BLOCK) tab.zero(i);
   for (int w = tid; w < nwords; w += BLOCK) cmask[w] = 0u;
+  for (int v = tid; v <= n; v += BLOCK) rp[v] = a.row_ptr[v];
   tab.sync();
   __syncthreads();
   // 2. gamma from the CSR entries
@@ -419,9 +473,8 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
       int64_t ttf = (int64_t)a.ten_num * fnew / a.ten_den;
       const bool capped = ttf > kTenureCap;
       if (capped) ttf = kTenureCap;
-      const int rs = a.row_ptr[vs], re = a.row_ptr[vs + 1];
-      for (int e = rs + lane; e < re; e += kWave) {
-        const int u = a.col_idx[e];
+      const int rs = rp[vs], re = rp[vs + 1];
+      auto update = [&](int u) {
         const uint32_t xu = cg[u];
         const int cu = (int)(xu & 0xffffu);
         tab.add(u * kp + old, -1);
@@ -433,7 +486,19 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, uint3
           cg[u] = xu + 0x10000u;
           if ((xu >> 16) == 0u) atomicOr(&cmask[u >> 5], 1u << (u & 31));
         }
+      };
+      // the first 8 x 64 neighbours: all loads issued before any is used
+      constexpr int kPre = 8;
+      int nb[kPre];
+#pragma unroll
+      for (int r = 0; r < kPre; ++r) {
+        const int e = rs + lane + r * kWave;
+        nb[r] = e < re ? a.col_idx[e] : -1;
       }
+#pragma unroll
+      for (int r = 0; r < kPre; ++r)
+        if (nb[r] >= 0) update(nb[r]);
+      for (int e = rs + kPre * kWave + lane; e < re; e += kWave) update(a.col_idx[e]);
       if (lane == 0) {
         tab.set_tabu(vs * kp + old, trel + Lt + (uint32_t)ttf);
         const uint32_t gnew = tab.gamma(vs * kp + cs);

@@ -30,7 +30,8 @@ template <int BLOCK, class Tab>
 __global__ __launch_bounds__(BLOCK) void tabucol_kernel(TabuArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int li = blockIdx.x;
-  uint32_t* gtab = a.gtab ? a.gtab + (size_t)li * (size_t)a.n * (size_t)tab_stride(a.k) : nullptr;
+  unsigned char* gtab =
+      a.gtab ? a.gtab + (size_t)li * (size_t)a.n * (size_t)tab_stride(a.k) * Tab::kGlobalBytes : nullptr;
   tabu_individual<BLOCK, Tab>(a, li, gtab, smem);
 }
 
@@ -86,11 +87,12 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
   if (table == DLM_TABLE_AUTO)
     table = tabu_layout(n, k, nw, TabLds16::kLdsBytes).bytes <= (uint64_t)lds_max ? DLM_TABLE_LDS16
                                                                                   : DLM_TABLE_GLOBAL16;
-  int eb = 0;
+  int eb = 0, gb = 0;
   switch (table) {
     case DLM_TABLE_LDS16: eb = TabLds16::kLdsBytes; break;
     case DLM_TABLE_LDS32: eb = TabLds32::kLdsBytes; break;
-    case DLM_TABLE_GLOBAL16: eb = 0; break;
+    case DLM_TABLE_GLOBAL16: eb = 0; gb = TabGlobal16::kGlobalBytes; break;
+    case DLM_TABLE_SPLIT16: eb = TabSplit16::kLdsBytes; gb = TabSplit16::kGlobalBytes; break;
     default: return set_error(DLM_E_INVAL, "dlm_tabu_batch: unknown table %d", table);
   }
   const uint64_t lds = tabu_layout(n, k, nw, eb).bytes;
@@ -101,10 +103,11 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
              make_key(p->seed), n, k, p->max_iters, p->ten_num, p->ten_den, p->ten_rand,
              p->ind_base, p->trace_cap};
   hipStream_t s = (hipStream_t)stream;
-  if (table == DLM_TABLE_GLOBAL16) {
-    const size_t bytes = (size_t)pop * n * tab_stride(k) * sizeof(uint32_t);
+  if (gb > 0) {
+    const size_t bytes = (size_t)pop * n * tab_stride(k) * gb;
     DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
-    int rc = launch_tab<TabGlobal16>(a, pop, block, lds, s);
+    int rc = table == DLM_TABLE_SPLIT16 ? launch_tab<TabSplit16>(a, pop, block, lds, s)
+                                        : launch_tab<TabGlobal16>(a, pop, block, lds, s);
     hipError_t e = hipFreeAsync(a.gtab, s);
     if (rc != DLM_OK) return rc;
     DLM_HIP(e);

@@ -37,7 +37,7 @@ def make_jobs(dlm, specs, seed=5):
 
 
 SPECS = [("gnp", 120, 0.5, 14, 9, 1500), ("planted", 300, 0.5, 9, 5, 2500),
-         ("gnp", 60, 0.3, 5, 13, 800), ("gnp", 400, 0.5, 90, 3, 1200),   # 400 x 90 table: device tier
+         ("gnp", 60, 0.3, 5, 13, 800), ("gnp", 600, 0.5, 90, 3, 1200),   # 600 x 90: split or device table
          ("planted", 200, 0.6, 20, 6, 2000)]
 
 

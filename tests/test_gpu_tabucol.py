@@ -96,7 +96,7 @@ def test_parity_shapes(dlm, dev, shape, block):
     compare(gpu, ref, ids, f"n{n} k{k} block{block}")
 
 
-@pytest.mark.parametrize("table", ["lds16", "lds32", "global16"])
+@pytest.mark.parametrize("table", ["lds16", "lds32", "global16", "split16"])
 def test_parity_tables(dlm, dev, table):
     g = gnp(180, 0.5, seed=7)
     k, T, pop = 19, 20000, 6   # long enough to cross the 16-bit expiry rebase
@@ -162,10 +162,10 @@ def test_gnp100_full(dlm, dev):
 
 
 def test_gnp500_full_size_sampled(dlm, dev):
-    """G(500, 0.5), k = 49, 8192 individuals x 100,000 iterations in one launch
-    (LDS16 table, 256 threads), exactly as the benchmark runs it; individuals
-    i = 128 j are replayed by the oracle."""
-    from bench import GNP500_BLOCK
+    """G(500, 0.5), k = 49, 8192 individuals x 100,000 iterations in one launch,
+    in the benchmark's launch configuration; individuals i = 128 j are
+    replayed by the oracle."""
+    from bench import GNP500_BLOCK, GNP500_TABLE
     w = workload("gnp500")
     g, k, T = w.graphs[0], w.k[0], w.iters[0]
     G = dlm.Graph.from_csr(g)
@@ -173,7 +173,7 @@ def test_gnp500_full_size_sampled(dlm, dev):
     col, _ = dlm.init_population(G, k, w.pop, seed=w.init_seed)
     starts = col.cpu().numpy()
     say("tabu gnp500 full size: 8192 x 100000")
-    r = dlm.tabu_batch(G, col, k, T, w.tabu_seed, block=GNP500_BLOCK, table="lds16")
+    r = dlm.tabu_batch(G, col, k, T, w.tabu_seed, block=GNP500_BLOCK, table=GNP500_TABLE)
     torch.cuda.synchronize()
     ids = np.arange(0, w.pop, w.extra["sample_stride"])
     ref = oracle.tabucol_batch(g, starts[ids], ids, k, T, seed=w.tabu_seed)
@@ -186,3 +186,17 @@ def test_gnp500_full_size_sampled(dlm, dev):
     assert (conf.cpu().numpy() == fb).all()
     st = r["stats"].cpu().numpy()
     assert (st[:, 0] + st[:, 1] == r["iters"].cpu().numpy()).all()
+
+
+def test_gnp500_split_table_sampled(dlm, dev):
+    """The split table (gamma in LDS, tabu expiries in device memory) on the
+    G(500, 0.5) shape with a reduced population and budget: same results as
+    the oracle on every individual."""
+    w = workload("gnp500")
+    g, k = w.graphs[0], w.k[0]
+    pop, T = 24, 20000
+    starts = oracle.init_random(g.n, k, pop, seed=w.init_seed)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=w.tabu_seed)
+    say("tabu gnp500 split16 pop=24 T=20000")
+    gpu = gpu_run(dlm, g, starts, k, T, w.tabu_seed, table="split16", block=256)
+    compare(gpu, ref, range(pop), "gnp500 split16")
