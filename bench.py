@@ -2,8 +2,8 @@
 
 Default workload (the configuration the headline metric is quoted on):
 G(500, 0.5) from seed 0, k = 49, population 8192, 100,000 tabu iterations
-per individual, 16-bit packed gamma/tabu table in LDS, 256 threads per
-workgroup.  One step = random population initialisation + one full TabuCol
+per individual, byte gamma in LDS with 16-bit tabu expiries in device memory
+(four individuals resident per CU), 256 threads per workgroup.  One step = random population initialisation + one full TabuCol
 pass over the population (every kernel of the search path); the graph is
 uploaded once, before timing.  Step s uses initial-colouring seed
 1 + s so every step searches new individuals.
@@ -25,33 +25,69 @@ import time
 import numpy as np
 
 GNP500_BLOCK = 256
-GNP500_TABLE = "lds16"
+GNP500_TABLE = "split8"
 LDS_PEAK_GBS = 256 * 128 * 2.4  # GB/s: 256 CUs x 128 B/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned vs plain"
+
+
+# HBM bytes per launch of the benchmarked TabuCol launch, from two rocprofv3
+# --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads
+# for a 1 GiB device-to-device copy.  Valid only for the kernel sources they
+# were taken on (digest below) and the same table and block; otherwise null.
+MEASURED_TRAFFIC = {"sources_sha256": None, "table": None, "block": None, "bytes": None}
+KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd/csrc/tabucol.hip",
+                  "paper_2109_05948_amd/csrc/dlm_common.h")
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(root, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(table: str, block: int):
+    m = MEASURED_TRAFFIC
+    if m["bytes"] is None or m["table"] != table or m["block"] != block:
+        return None
+    return m["bytes"] if kernel_sources_digest() == m["sources_sha256"] else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def lds_bytes(st: np.ndarray, k: int, s_gamma: int = 2, s_tabu: int = 2, s_col: int = 2) -> float:
+# bytes of one table entry by tier: (gamma in LDS, tabu in LDS, gamma in device memory, tabu in device memory)
+TIER_BYTES = {"lds16": (2, 2, 0, 0), "lds32": (4, 4, 0, 0), "split16": (2, 0, 0, 2),
+              "split8": (1, 0, 0, 2), "global16": (0, 0, 2, 2)}
+
+
+def lds_bytes(st: np.ndarray, k: int, table: str = "lds16", s_col: int = 2) -> float:
     """Algorithmic LDS bytes of a TabuCol run from its counters.
 
-    Per iteration: C_t (k-1) (s_gamma + s_tabu) [candidate scan]
-                 + C_t (s_gamma + s_col)         [current colour and gamma]
-    per move:      deg(v*) (4 s_gamma + s_col)   [neighbour gamma updates]
-                 + s_tabu + s_col                [tabu entry, colour]
+    With g, u the LDS bytes of a gamma and a tabu entry of the table tier:
+    per iteration: C_t (k-1) (g + u)     [candidate scan]
+                 + C_t (g + s_col)       [current colour and its gamma]
+    per move:      deg(v*) (4 g + s_col) [neighbour gamma updates, read + write]
+                 + u + s_col             [tabu entry, colour of v*]
     st columns: 0 moves, 2 sum C_t, 3 sum deg(v*).
     """
+    g, u = TIER_BYTES[table][:2]
     moves, sum_c, sum_deg = st[:, 0].sum(), st[:, 2].sum(), st[:, 3].sum()
-    return float(sum_c * ((k - 1) * (s_gamma + s_tabu) + s_gamma + s_col)
-                 + sum_deg * (4 * s_gamma + s_col) + moves * (s_tabu + s_col))
+    return float(sum_c * ((k - 1) * (g + u) + g + s_col) + sum_deg * (4 * g + s_col) + moves * (u + s_col))
 
 
-def hbm_bytes(st: np.ndarray) -> float:
-    """Algorithmic HBM bytes: the CSR row of v* (4 B per neighbour) per move."""
-    return float(4 * st[:, 3].sum())
+def hbm_bytes(st: np.ndarray, k: int, table: str = "lds16") -> float:
+    """Algorithmic device-memory bytes: the CSR row of v* (4 B per neighbour)
+    per move, plus the table entries the tier keeps in device memory (same
+    terms as the LDS model with the device-memory entry sizes)."""
+    g, u = TIER_BYTES[table][2:]
+    moves, sum_c, sum_deg = st[:, 0].sum(), st[:, 2].sum(), st[:, 3].sum()
+    return float(4 * sum_deg + sum_c * ((k - 1) * (g + u) + g) + sum_deg * 4 * g + moves * u)
 
 
 def cpu_baseline(g, k, T, seed, init_seed, count, threads):
@@ -151,8 +187,9 @@ def main():
     log(f"timed {args.steps} steps in {dt:.3f} s; tabu kernel {kern_ms:.2f} ms/launch; "
         f"moves {moves}; no-ops {int(st[:, 1].sum())}")
 
-    per_launch_lds = lds_bytes(st, k) / args.steps
-    per_launch_hbm = hbm_bytes(st) / args.steps
+    traffic = measured_traffic(args.table, args.block) if pop == w.pop else None
+    per_launch_lds = lds_bytes(st, k, args.table) / args.steps
+    per_launch_hbm = hbm_bytes(st, k, args.table) / args.steps
     lds_gbs = per_launch_lds / (kern_ms * 1e-3) / 1e9
     hbm_gbs = per_launch_hbm / (kern_ms * 1e-3) / 1e9
     out = {
@@ -172,11 +209,11 @@ def main():
                    "population": pop, "iters_per_individual": T, "block": args.block,
                    "table": args.table, "parallelism": "population (one workgroup per individual)"},
         "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": None,
+                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": traffic,
                      "kernel": "tabucol_kernel", "kernel_ms": kern_ms,
                      "bytes_per_launch": per_launch_lds},
         "roofline_hbm": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": None},
+                         "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "tabu_kernel_moves_per_s": moves / args.steps / (kern_ms * 1e-3),
     }
     if not args.no_cpu_baseline and args.workload == "gnp500":

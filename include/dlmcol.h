@@ -108,11 +108,14 @@ int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, uint64_t see
  *     L = floor(w0 * ten_rand / 2^32), w0 = Philox(seed; ind, t, 0, 0x80000001);
  *   the best colouring met (smallest f) is kept.
  * ---------------------------------------------------------------------- */
-#define DLM_TABLE_AUTO 0       /* packed 16-bit in LDS if it fits, else global */
+#define DLM_TABLE_AUTO 0       /* LDS16 or SPLIT8, whichever keeps more workgroups per CU; GLOBAL16 if neither fits */
 #define DLM_TABLE_LDS16 1      /* 32-bit word per (v,c): gamma 16 bits | tabu 16 bits, LDS */
 #define DLM_TABLE_LDS32 2      /* 64-bit word per (v,c): gamma int32 | tabu expiry, LDS */
 #define DLM_TABLE_GLOBAL16 3   /* packed 16-bit words in device memory (large n*k) */
 #define DLM_TABLE_SPLIT16 4    /* gamma 16 bits in LDS, tabu 16 bits in device memory */
+#define DLM_TABLE_SPLIT8 5     /* gamma 8 bits in LDS, tabu 16 bits in device memory; an individual
+                                  whose colour classes would pass 255 vertices is rerun from its
+                                  start with GLOBAL16 (same results) */
 
 typedef struct dlm_tabu_params {
   int32_t k;          /* colours, 1 <= k <= 32767 */
@@ -160,8 +163,10 @@ int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
  * bit-identical results.  Work items (graph, individual) are taken
  * longest-first from an atomic queue by a grid sized to the device's
  * resident capacity; graphs whose table fits the LDS budget use the LDS16
- * table, graphs whose 16-bit gamma alone fits use the split table (expiries
- * in device memory), the others the device-memory table.  A plan captures the queue
+ * table, graphs whose byte gamma alone fits use the SPLIT8 table (expiries in
+ * device memory; an individual whose colour classes would pass 255 vertices is
+ * rerun in place with the device-memory table, same results), the others the
+ * device-memory table.  A plan captures the queue
  * reset and the persistent kernel into a hipGraph once; each launch replays
  * it on the caller's stream and searches whatever the item buffers hold.
  * The plan keeps the item pointers: buffers and graphs must outlive it.

@@ -115,6 +115,14 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   return readlane(x, 0) + readlane(x, 16) + readlane(x, 32) + readlane(x, 48);
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  x = min(x, dpp_mov<dpp::kXor1>(x));
+  x = min(x, dpp_mov<dpp::kXor2>(x));
+  x = min(x, dpp_mov<dpp::kHalfMirror>(x));
+  x = min(x, dpp_mov<dpp::kMirror>(x));
+  return min(min(readlane(x, 0), readlane(x, 16)), min(readlane(x, 32), readlane(x, 48)));
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   x = max(x, dpp_mov<dpp::kXor1>(x));
   x = max(x, dpp_mov<dpp::kXor2>(x));

@@ -6,11 +6,12 @@
 // device keeps resident at the launch's LDS size; each workgroup pops items
 // from an atomic counter until the queue is empty, so every workgroup exits.
 // A graph whose table fits the launch's LDS budget runs the LDS16 table, one
-// whose gamma alone fits runs the split table (expiries in device memory),
-// the others the device-memory table; device storage is one slot per
-// workgroup.  The
-// search itself is the same function as dlm_tabu_batch's, so trajectories
-// are identical to single-graph runs with the same seeds and indices.
+// whose byte gamma alone fits runs the SPLIT8 table (expiries in device
+// memory, a rerun with the device-memory table in the same slot if a colour
+// class would pass 255 vertices), the others the device-memory table; device
+// storage is one slot per workgroup.  The search itself is the same function
+// as dlm_tabu_batch's, so trajectories are identical to single-graph runs
+// with the same seeds and indices.
 #include <algorithm>
 #include <chrono>
 #include <map>
@@ -24,7 +25,7 @@ namespace dlm {
 
 struct MultiDesc {
   TabuArgs a;
-  int32_t tier;        // 0 = LDS16, 1 = GLOBAL16, 2 = SPLIT16
+  int32_t tier;        // 0 = LDS16, 1 = GLOBAL16, 3 = SPLIT8 (GLOBAL16 rerun past 255 per class)
   int32_t first_item;  // items [first_item, first_item + pop) belong to this graph
   int32_t pop;
   int32_t pad;
@@ -53,9 +54,26 @@ __global__ __launch_bounds__(BLOCK) void tabu_multi_kernel(const MultiDesc* __re
     while (g + 1 < ndesc && descs[g + 1].first_item <= item) ++g;
     const MultiDesc& d = descs[g];
     const int li = item - d.first_item;
-    if (d.tier == 0) tabu_individual<BLOCK, TabLds16>(d.a, li, nullptr, smem);
-    else if (d.tier == 2) tabu_individual<BLOCK, TabSplit16>(d.a, li, gtab, smem);
-    else tabu_individual<BLOCK, TabGlobal16>(d.a, li, gtab, smem);
+    if (d.tier == 0) {
+      tabu_individual<BLOCK, TabLds16>(d.a, li, nullptr, smem);
+    } else if (d.tier == 3) {
+      // byte gamma; the start colouring waits behind the slot's table for a
+      // 16-bit rerun if a colour class would pass 255 vertices
+      const int n = d.a.n;
+      int16_t* gcol = d.a.colors + (size_t)li * n;
+      int16_t* save = reinterpret_cast<int16_t*>(gtab + tab_entries(n, d.a.k) * TabGlobal16::kGlobalBytes);
+      for (int v = threadIdx.x; v < n; v += BLOCK) save[v] = gcol[v];
+      __syncthreads();
+      tabu_individual<BLOCK, TabSplit8>(d.a, li, gtab, smem);
+      __syncthreads();
+      if (d.a.iters[li] == -2) {
+        for (int v = threadIdx.x; v < n; v += BLOCK) gcol[v] = save[v];
+        __syncthreads();
+        tabu_individual<BLOCK, TabGlobal16>(d.a, li, gtab, smem);
+      }
+    } else {
+      tabu_individual<BLOCK, TabGlobal16>(d.a, li, gtab, smem);
+    }
   }
 }
 
@@ -170,26 +188,28 @@ int dlm_multi_plan_create(const dlm_multi_item* items, int32_t count, const dlm_
                    it.stats_dev, it.hash_dev, nullptr, nullptr, make_key(it.seed), n, it.k, it.max_iters,
                    it.ten_num, it.ten_den, it.ten_rand, it.ind_base, 0};
     const uint64_t lds16 = tabu_layout(n, it.k, nw, TabLds16::kLdsBytes).bytes;
-    const uint64_t ldss = tabu_layout(n, it.k, nw, TabSplit16::kLdsBytes).bytes;
+    const uint64_t lds8 = tabu_layout(n, it.k, nw, TabSplit8::kLdsBytes).bytes;
     if ((int64_t)lds16 <= budget) {
       d.tier = 0;
       lds = std::max<size_t>(lds, lds16);
-    } else if ((int64_t)ldss <= budget) {
-      d.tier = 2;
+    } else if ((int64_t)lds8 <= budget) {
+      d.tier = 3;
       ++p->n_global;
-      lds = std::max<size_t>(lds, ldss);
-      p->slot_words = std::max<int64_t>(p->slot_words, ((int64_t)n * tab_stride(it.k) * 2 + 3) / 4);
+      lds = std::max<size_t>(lds, lds8);
+      // packed 16-bit table for a rerun (the byte run's expiries use the first half) + the start colouring
+      p->slot_words = std::max<int64_t>(p->slot_words, (int64_t)tab_entries(n, it.k) + (n + 1) / 2);
     } else {
       d.tier = 1;
       ++p->n_global;
       lds = std::max<size_t>(lds, tabu_layout(n, it.k, nw, 0).bytes);
-      p->slot_words = std::max<int64_t>(p->slot_words, (int64_t)n * tab_stride(it.k));
+      p->slot_words = std::max<int64_t>(p->slot_words, (int64_t)tab_entries(n, it.k));
     }
     d.first_item = first;
     d.pop = it.pop;
     first += it.pop;
     descs.push_back(d);
   }
+  p->slot_words = (p->slot_words + 3) & ~int64_t(3);  // 16-byte aligned slots
   p->total = first;
   p->ndesc = (int32_t)descs.size();
   p->lds = lds;

@@ -8,140 +8,148 @@
 
 namespace dlm {
 
-constexpr int kBias = 32768;          // delta + kBias >= 0 for |delta| < 2^15
-constexpr int kRebaseEvery = 16384;   // LDS16: expiry origin moves every 2^14 iterations
+constexpr int kBias = 32768;             // delta + kBias >= 0 for |delta| < 2^15
+constexpr int kRebaseEvery = 16384;      // 16-bit expiries: the origin moves every 2^14 iterations
+constexpr uint32_t kPadGamma = 0x7fffu;  // gamma stored in the padding colours k .. kp-1
+constexpr uint32_t kNone = 0xffffffffu;  // no admissible candidate
+constexpr int kStage = 128;              // tied moves a wave hashes in one staged pass
+
+// Table encoding, common to every storage policy:
+//  * the entry (v, col v) of a vertex's current colour holds the expiry
+//    kInf, which no iteration reaches, so it is never admissible by tenure;
+//    its delta is 0 and the aspiration needs f + delta < f_best <= f, so it
+//    is never admissible at all;
+//  * the padding colours c in [k, kp) hold a large gamma (kPadGamma, or
+//    255 for byte gamma) and expiry kInf: delta >= 1, never admissible
+//    either.
+// The scan therefore needs no test on the colour of a candidate.  A vertex's
+// old colour gets its real expiry when the vertex leaves it, the new colour
+// gets kInf; the expiry an entry held while it was the current colour is
+// never read (the move rule excludes c = col v).
 
 // ---------------------------------------------------------------------------
-// Table storage policies.
+// Table storage policies.  quad(i, thr, g, fr) reads the four entries i..i+3
+// (i a multiple of 4) and reports gamma and "not tabu" (expiry <= trel, with
+// thr = free_thr(trel)).
 struct TabLds16 {
+  static constexpr bool kBounded = false;
   static constexpr bool kRebase = true;
   static constexpr int kLdsBytes = 4;
-  uint32_t* w;
   static constexpr int kGlobalBytes = 0;
+  static constexpr uint32_t kInf = 0xffffu;
+  uint32_t* w;  // gamma low 16 bits, expiry (relative to the rebased origin) high 16 bits
   __device__ static TabLds16 make(unsigned char* lds, unsigned char*) {
     return TabLds16{reinterpret_cast<uint32_t*>(lds)};
   }
-  __device__ __forceinline__ void zero(int i) { w[i] = 0u; }
+  __device__ __forceinline__ void init(int i, bool pad) { w[i] = pad ? (kPadGamma | (kInf << 16)) : 0u; }
   __device__ __forceinline__ void add(int i, int d) { atomicAdd(&w[i], (uint32_t)d); }
   __device__ __forceinline__ uint32_t gamma(int i) const { return w[i] & 0xffffu; }
-  __device__ __forceinline__ void read(int i, uint32_t& g, uint32_t& ex) const {
-    const uint32_t x = w[i];
-    g = x & 0xffffu;
-    ex = x >> 16;
-  }
-  // four consecutive entries (i a multiple of 4: one 16-byte LDS read)
-  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
+  // expiry <= trel  <=>  the packed word <= (trel << 16) | 0xffff
+  __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return (trel << 16) | 0xffffu; }
+  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
     const uint4 x = *reinterpret_cast<const uint4*>(w + i);
-    g[0] = x.x & 0xffffu; ex[0] = x.x >> 16;
-    g[1] = x.y & 0xffffu; ex[1] = x.y >> 16;
-    g[2] = x.z & 0xffffu; ex[2] = x.z >> 16;
-    g[3] = x.w & 0xffffu; ex[3] = x.w >> 16;
+    g[0] = x.x & 0xffffu; fr[0] = x.x <= thr;
+    g[1] = x.y & 0xffffu; fr[1] = x.y <= thr;
+    g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
+    g[3] = x.w & 0xffffu; fr[3] = x.w <= thr;
   }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) {
     reinterpret_cast<uint16_t*>(w)[2 * i + 1] = (uint16_t)ex;
   }
   __device__ __forceinline__ void rebase(int i) {
     const uint32_t x = w[i];
-    const uint32_t e = x >> 16;
-    w[i] = (x & 0xffffu) | ((e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u) << 16);
+    uint32_t e = x >> 16;
+    if (e != kInf) e = e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u;
+    w[i] = (x & 0xffffu) | (e << 16);
   }
-  __device__ __forceinline__ void sync() {}
 };
 
 struct TabLds32 {
+  static constexpr bool kBounded = false;
   static constexpr bool kRebase = false;
   static constexpr int kLdsBytes = 8;
-  uint32_t* w;  // w[2i] = gamma, w[2i+1] = absolute expiry
   static constexpr int kGlobalBytes = 0;
+  static constexpr uint32_t kInf = 0xffffffffu;
+  uint32_t* w;  // w[2i] = gamma, w[2i+1] = absolute expiry
   __device__ static TabLds32 make(unsigned char* lds, unsigned char*) {
     return TabLds32{reinterpret_cast<uint32_t*>(lds)};
   }
-  __device__ __forceinline__ void zero(int i) {
-    w[2 * i] = 0u;
-    w[2 * i + 1] = 0u;
+  __device__ __forceinline__ void init(int i, bool pad) {
+    w[2 * i] = pad ? kPadGamma : 0u;
+    w[2 * i + 1] = pad ? kInf : 0u;
   }
   __device__ __forceinline__ void add(int i, int d) { atomicAdd(&w[2 * i], (uint32_t)d); }
   __device__ __forceinline__ uint32_t gamma(int i) const { return w[2 * i]; }
-  __device__ __forceinline__ void read(int i, uint32_t& g, uint32_t& ex) const {
-    const uint2 x = reinterpret_cast<const uint2*>(w)[i];
-    g = x.x;
-    ex = x.y;
-  }
-  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
+  __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
+  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
     const uint4 x = *reinterpret_cast<const uint4*>(w + 2 * i);
     const uint4 y = *reinterpret_cast<const uint4*>(w + 2 * i + 4);
-    g[0] = x.x; ex[0] = x.y; g[1] = x.z; ex[1] = x.w;
-    g[2] = y.x; ex[2] = y.y; g[3] = y.z; ex[3] = y.w;
+    g[0] = x.x; fr[0] = x.y <= thr; g[1] = x.z; fr[1] = x.w <= thr;
+    g[2] = y.x; fr[2] = y.y <= thr; g[3] = y.z; fr[3] = y.w <= thr;
   }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { w[2 * i + 1] = ex; }
   __device__ __forceinline__ void rebase(int) {}
-  __device__ __forceinline__ void sync() {}
 };
 
-// Packed 16-bit words in device memory.  Reads are device-coherent loads so
-// that a wave sees the atomic updates made by another wave of its workgroup.
+// Packed 16-bit words in device memory.  Only the waves of one workgroup
+// touch a table, and every read of an entry written by another wave comes
+// after a workgroup barrier, so plain loads and stores and workgroup-scope
+// atomics are enough (no device-scope fence, which would write back and
+// invalidate L2).
 struct TabGlobal16 {
+  static constexpr bool kBounded = false;
   static constexpr bool kRebase = true;
   static constexpr int kLdsBytes = 0;
-  uint32_t* w;
   static constexpr int kGlobalBytes = 4;
+  static constexpr uint32_t kInf = 0xffffu;
+  uint32_t* w;
   __device__ static TabGlobal16 make(unsigned char*, unsigned char* g) {
     return TabGlobal16{reinterpret_cast<uint32_t*>(g)};
   }
-  __device__ __forceinline__ uint32_t ld(int i) const {
-    return __hip_atomic_load(&w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __device__ __forceinline__ void zero(int i) {
-    __hip_atomic_store(&w[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  __device__ __forceinline__ uint32_t ld(int i) const { return w[i]; }
+  __device__ __forceinline__ void st(int i, uint32_t x) { w[i] = x; }
+  __device__ __forceinline__ void init(int i, bool pad) { st(i, pad ? (kPadGamma | (kInf << 16)) : 0u); }
   __device__ __forceinline__ void add(int i, int d) {
-    __hip_atomic_fetch_add(&w[i], (uint32_t)d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&w[i], (uint32_t)d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __device__ __forceinline__ uint32_t gamma(int i) const { return ld(i) & 0xffffu; }
-  __device__ __forceinline__ void read(int i, uint32_t& g, uint32_t& ex) const {
-    const uint32_t x = ld(i);
-    g = x & 0xffffu;
-    ex = x >> 16;
+  __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return (trel << 16) | 0xffffu; }
+  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
+    const uint4 x = *reinterpret_cast<const uint4*>(w + i);
+    g[0] = x.x & 0xffffu; fr[0] = x.x <= thr;
+    g[1] = x.y & 0xffffu; fr[1] = x.y <= thr;
+    g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
+    g[3] = x.w & 0xffffu; fr[3] = x.w <= thr;
   }
-  __device__ __forceinline__ void read4(int i, uint32_t g[4], uint32_t ex[4]) const {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t x = ld(i + q);
-      g[q] = x & 0xffffu;
-      ex[q] = x >> 16;
-    }
-  }
-  __device__ __forceinline__ void set_tabu(int i, uint32_t ex) {
-    // only the high half changes; the low half of row v* is not touched by this move
-    const uint32_t x = ld(i);
-    __hip_atomic_store(&w[i], (x & 0xffffu) | (ex << 16), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  // only the high half changes; the low half of row v* is not touched by this move
+  __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { st(i, (ld(i) & 0xffffu) | (ex << 16)); }
   __device__ __forceinline__ void rebase(int i) {
     const uint32_t x = ld(i);
-    const uint32_t e = x >> 16;
-    __hip_atomic_store(&w[i], (x & 0xffffu) | ((e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u) << 16),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t e = x >> 16;
+    if (e != kInf) e = e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u;
+    st(i, (x & 0xffffu) | (e << 16));
   }
-  // complete this wave's table updates before the next workgroup barrier
-  __device__ __forceinline__ void sync() { __threadfence(); }
 };
 
 // Split storage: gamma (16 bits) in LDS, tabu expiries (16 bits, relative
 // to the rebased origin) in device memory.  Half the LDS of LDS16, so twice
 // as many individuals fit on a CU; the expiry rows of the resident
-// individuals stay in L2.  Expiries are read with device-coherent loads.
+// individuals stay in L2.  As for the device table, plain accesses ordered by
+// workgroup barriers suffice.
 struct TabSplit16 {
+  static constexpr bool kBounded = false;
   static constexpr bool kRebase = true;
   static constexpr int kLdsBytes = 2;
   static constexpr int kGlobalBytes = 2;
+  static constexpr uint32_t kInf = 0xffffu;
   uint16_t* g;   // LDS gamma
   uint16_t* tb;  // device tabu expiries
   __device__ static TabSplit16 make(unsigned char* lds, unsigned char* gm) {
     return TabSplit16{reinterpret_cast<uint16_t*>(lds), reinterpret_cast<uint16_t*>(gm)};
   }
-  __device__ __forceinline__ void zero(int i) {
-    g[i] = 0;
-    tb[i] = 0;
+  __device__ __forceinline__ void init(int i, bool pad) {
+    g[i] = (uint16_t)(pad ? kPadGamma : 0u);
+    tb[i] = (uint16_t)(pad ? kInf : 0u);
   }
   __device__ __forceinline__ void add(int i, int d) {
     // 16-bit add inside the containing 32-bit LDS word; a decrement only
@@ -150,25 +158,72 @@ struct TabSplit16 {
     atomicAdd(reinterpret_cast<uint32_t*>(g) + (i >> 1), (i & 1) ? (inc << 16) : (d > 0 ? 1u : 0xffffffffu));
   }
   __device__ __forceinline__ uint32_t gamma(int i) const { return g[i]; }
-  __device__ __forceinline__ uint32_t ldt(int i) const {
-    const uint32_t w = __hip_atomic_load(reinterpret_cast<const uint32_t*>(tb) + (i >> 1), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-    return (i & 1) ? (w >> 16) : (w & 0xffffu);
-  }
-  __device__ __forceinline__ void read4(int i, uint32_t gg[4], uint32_t ex[4]) const {
+  __device__ __forceinline__ uint32_t ldt(int i) const { return tb[i]; }
+  __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
+  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t gg[4], bool fr[4]) const {
     const uint2 x = *reinterpret_cast<const uint2*>(g + i);
-    const uint64_t t = __hip_atomic_load(reinterpret_cast<const uint64_t*>(tb + i), __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t = *reinterpret_cast<const uint64_t*>(tb + i);
     gg[0] = x.x & 0xffffu; gg[1] = x.x >> 16; gg[2] = x.y & 0xffffu; gg[3] = x.y >> 16;
-    ex[0] = (uint32_t)t & 0xffffu; ex[1] = (uint32_t)(t >> 16) & 0xffffu;
-    ex[2] = (uint32_t)(t >> 32) & 0xffffu; ex[3] = (uint32_t)(t >> 48);
+    fr[0] = ((uint32_t)t & 0xffffu) <= thr;
+    fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
+    fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
+    fr[3] = (uint32_t)(t >> 48) <= thr;
   }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { tb[i] = (uint16_t)ex; }
   __device__ __forceinline__ void rebase(int i) {
-    const uint32_t e = ldt(i);
+    uint32_t e = ldt(i);
+    if (e == kInf) return;
     tb[i] = (uint16_t)(e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u);
   }
-  __device__ __forceinline__ void sync() { __threadfence(); }
+};
+
+
+// Byte gamma in LDS, tabu expiries (16 bits) in device memory: a quarter of
+// the LDS of LDS16.  Exact while every colour class has at most 255
+// vertices (gamma[v][c] never exceeds the size of class c); the search body
+// keeps the class sizes and gives up on an individual (iters = -2) before a
+// move would break the bound, and the caller reruns it from its start
+// colouring with 16-bit gamma.
+struct TabSplit8 {
+  static constexpr bool kBounded = true;
+  static constexpr bool kRebase = true;
+  static constexpr int kLdsBytes = 1;
+  static constexpr int kGlobalBytes = 2;
+  static constexpr uint32_t kInf = 0xffffu;
+  static constexpr uint32_t kPad = 0xffu;  // padding gamma: delta >= 1, never admissible
+  uint8_t* g;    // LDS gamma
+  uint16_t* tb;  // device tabu expiries
+  __device__ static TabSplit8 make(unsigned char* lds, unsigned char* gm) {
+    return TabSplit8{reinterpret_cast<uint8_t*>(lds), reinterpret_cast<uint16_t*>(gm)};
+  }
+  __device__ __forceinline__ void init(int i, bool pad) {
+    g[i] = (uint8_t)(pad ? kPad : 0u);
+    tb[i] = (uint16_t)(pad ? kInf : 0u);
+  }
+  __device__ __forceinline__ void add(int i, int d) {
+    // byte add inside the containing 32-bit word: a decrement only happens on
+    // a positive count and an increment never reaches 256, so no carry or
+    // borrow leaves the byte
+    const uint32_t one = 1u << (8 * (i & 3));
+    atomicAdd(reinterpret_cast<uint32_t*>(g) + (i >> 2), d > 0 ? one : 0u - one);
+  }
+  __device__ __forceinline__ uint32_t gamma(int i) const { return g[i]; }
+  __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
+  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t gg[4], bool fr[4]) const {
+    const uint32_t x = *reinterpret_cast<const uint32_t*>(g + i);
+    const uint64_t t = *reinterpret_cast<const uint64_t*>(tb + i);
+    gg[0] = x & 0xffu; gg[1] = (x >> 8) & 0xffu; gg[2] = (x >> 16) & 0xffu; gg[3] = x >> 24;
+    fr[0] = ((uint32_t)t & 0xffffu) <= thr;
+    fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
+    fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
+    fr[3] = (uint32_t)(t >> 48) <= thr;
+  }
+  __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { tb[i] = (uint16_t)ex; }
+  __device__ __forceinline__ void rebase(int i) {
+    const uint32_t e = tb[i];
+    if (e == kInf) return;
+    tb[i] = (uint16_t)(e > (uint32_t)kRebaseEvery ? e - kRebaseEvery : 0u);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -188,81 +243,123 @@ struct TabuArgs {
 };
 
 struct TabuLayout {
-  uint64_t tab, cg, conf, cmask, rp, red, redc, red2, sc, bytes;
+  uint64_t tab, cg, list, pos, rp, red, stage, csize, sc, bytes;
+  int32_t cap;  // conflict-list capacity (entries)
 };
 
 // Table rows are padded to a multiple of 4 colours so that a quad of
-// candidates is one aligned 16-byte read.
+// candidates is one aligned 16-byte read.  Row n is all padding: conflict
+// list entries that no longer name a conflicting vertex point at it.
 __host__ __device__ constexpr int tab_stride(int k) { return (k + 3) & ~3; }
+__host__ __device__ constexpr uint64_t tab_entries(int n, int k) { return (uint64_t)(n + 1) * tab_stride(k); }
 
 __host__ __device__ inline TabuLayout tabu_layout(int n, int k, int nw, int entry_bytes) {
   TabuLayout L;
   uint64_t o = 0;
   L.tab = o;
-  o += (((uint64_t)n * tab_stride(k) * entry_bytes) + 15u) & ~15ull;
+  o += ((tab_entries(n, k) * entry_bytes) + 15u) & ~15ull;
   L.cg = o;
   o += align16(4u * n);
-  L.conf = o;
-  o += align16(2u * n);
-  L.cmask = o;
-  o += align16(4u * ((n + 31) / 32));
+  L.cap = 2 * n + 32;
+  L.list = o;
+  o += align16(4u * L.cap);
+  L.pos = o;
+  o += align16(4u * n);
   L.rp = o;
   o += align16(4u * (n + 1));
   L.red = o;
-  o += 16u * nw;
-  L.redc = o;
-  o += align16(8u * nw);
-  L.red2 = o;
-  o += 16u * nw;
+  o += 2u * 16u * nw;
+  L.stage = o;
+  o += (uint64_t)nw * 4u * (kStage + 4);
+  L.csize = o;
+  o += align16(4u * tab_stride(k));
   L.sc = o;
   o += 16;
   L.bytes = o;
   return L;
 }
 
-// Wave 0 rebuilds the list of conflicting vertices from the mask.  The order
-// of the list is irrelevant: the chosen move is a total-order minimum.
-__device__ __forceinline__ void build_conflict_list(const uint32_t* cmask, uint16_t* conf,
-                                                    int32_t* count, int nwords, int lane) {
-  if (lane == 0) *count = 0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int w = lane; w < nwords; w += kWave) {
-    uint32_t m = cmask[w];
-    if (m) {
-      int pos = atomicAdd(count, __popc(m));
-      while (m) {
-        const int b = __ffs(m) - 1;
-        m &= m - 1;
-        conf[pos++] = (uint16_t)(w * 32 + b);
-      }
+constexpr uint32_t kNoPos = 0xffffffffu;
+
+// Wave 0 rebuilds the conflict list from cg (cg[v] = col v | gamma[v][col v] << 16):
+// the conflicting vertices in vertex order as (gamma[v][col v] << 16) | v,
+// pos[v] = index of v in the list or kNoPos.  Returns the list length.
+__device__ __forceinline__ int build_conflict_list(const uint32_t* cg, uint32_t* list, uint32_t* pos, int n,
+                                                   int lane) {
+  int base = 0;
+  for (int v0 = 0; v0 < n; v0 += 4 * kWave) {
+    uint32_t x[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = v0 + r * kWave + lane;
+      x[r] = v < n ? cg[v] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = v0 + r * kWave + lane;
+      const bool cf = x[r] >= 0x10000u;
+      const uint64_t m = __ballot(cf);
+      const int p = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (cf) list[p] = (x[r] & 0xffff0000u) | (uint32_t)v;
+      if (v < n) pos[v] = cf ? (uint32_t)p : kNoPos;
+      base += __popcll(m);
     }
   }
+  return base;
+}
+
+// Slots for the active lanes of a wave whose pred is true: one LDS atomic
+// per wave on *counter; returns counter's old value + the lane's rank.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred, int lane) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const int leader = __builtin_ctzll(m);
+  uint32_t b = 0;
+  if (lane == leader) b = atomicAdd(counter, (uint32_t)__popcll(m));
+  b = readlane(b, leader);
+  return b + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // One individual (row li of a.colors) searched by the calling workgroup.
 // gtab: the device-memory part of this workgroup's table (global and split tiers).
+//
+// The conflict list holds one live entry (gamma[v][col v] << 16 | v) per
+// conflicting vertex and tombstones (0 << 16 | n, the all-padding row) for
+// vertices that stopped conflicting; the move updates it in place and appends
+// new conflicting vertices, and it is rebuilt when tombstones pass a quarter
+// of it.  The chosen move is a minimum over a set, so list order is free.
 template <int BLOCK, class Tab>
 __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsigned char* gtab,
                                                 unsigned char* smem) {
   constexpr int NW = BLOCK / kWave;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const uint32_t ind = (uint32_t)(a.ind_base + li);
-  const int n = a.n, k = a.k, kp = tab_stride(k), nk = n * kp;
-  const int nwords = (n + 31) >> 5;
+  const int n = a.n, k = a.k, kp = tab_stride(k), nk = (int)tab_entries(n, k);
   const TabuLayout L = tabu_layout(n, k, NW, Tab::kLdsBytes);
   Tab tab = Tab::make(smem + L.tab, gtab);
   uint32_t* cg = reinterpret_cast<uint32_t*>(smem + L.cg);
-  uint16_t* conf = reinterpret_cast<uint16_t*>(smem + L.conf);
-  uint32_t* cmask = reinterpret_cast<uint32_t*>(smem + L.cmask);
-  uint64_t* red = reinterpret_cast<uint64_t*>(smem + L.red);
-  uint32_t* redc = reinterpret_cast<uint32_t*>(smem + L.redc);
-  uint64_t* red2 = reinterpret_cast<uint64_t*>(smem + L.red2);
-  int32_t* sc = reinterpret_cast<int32_t*>(smem + L.sc);
-  int32_t* rp = reinterpret_cast<int32_t*>(smem + L.rp);  // CSR row offsets, cached
+  uint32_t* list = reinterpret_cast<uint32_t*>(smem + L.list);
+  uint32_t* pos = reinterpret_cast<uint32_t*>(smem + L.pos);
+  uint4* red = reinterpret_cast<uint4*>(smem + L.red);
+  uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);  // per wave: kStage tied moves + a counter
+  uint32_t* csize = reinterpret_cast<uint32_t*>(smem + L.csize);  // class sizes (byte gamma only)
+  uint32_t* sc = reinterpret_cast<uint32_t*>(smem + L.sc);  // [0] list length, [1] tombstones
+  int32_t* rp = reinterpret_cast<int32_t*>(smem + L.rp);    // CSR row offsets, cached
   int16_t* gcol = a.colors + (size_t)li * n;
+  const uint32_t kTomb = (uint32_t)n;
 
-  // 1. start colouring (rejected whole if a colour is outside [0, k)), empty table and mask
+  auto rebuild = [&]() {
+    if (wid == 0) {
+      const int c = build_conflict_list(cg, list, pos, n, lane);
+      if (lane == 0) {
+        sc[0] = (uint32_t)c;
+        sc[1] = 0u;
+      }
+    }
+    __syncthreads();
+  };
+
+  // 1. start colouring (rejected whole if a colour is outside [0, k)), empty table
   int bad = 0;
   for (int v = tid; v < n; v += BLOCK) {
     const int c = gcol[v];
@@ -276,35 +373,42 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     }
     return;
   }
-  for (int i = tid; i < nk; i += BLOCK) tab.zero(i);
-  for (int w = tid; w < nwords; w += BLOCK) cmask[w] = 0u;
+  for (int i = tid; i < nk; i += BLOCK) tab.init(i, i >= n * kp || i - (i / kp) * kp >= k);
   for (int v = tid; v <= n; v += BLOCK) rp[v] = a.row_ptr[v];
-  tab.sync();
+  if (Tab::kBounded)
+    for (int c = tid; c < kp; c += BLOCK) csize[c] = 0u;
   __syncthreads();
-  // 2. gamma from the CSR entries
+  // 2. gamma from the CSR entries (and the class sizes)
   const int nnz = a.row_ptr[n];
+  if (Tab::kBounded) {
+    for (int v = tid; v < n; v += BLOCK) atomicAdd(&csize[cg[v] & 0xffffu], 1u);
+    __syncthreads();
+    int big = 0;
+    for (int c = tid; c < k; c += BLOCK) big |= csize[c] > 255u;
+    if (__syncthreads_or(big)) {  // a class too large for byte gamma: left to the 16-bit rerun
+      if (tid == 0) a.iters[li] = -2;
+      return;
+    }
+  }
   for (int e = tid; e < nnz; e += BLOCK) tab.add(a.erow[e] * kp + (int)(cg[a.col_idx[e]] & 0xffffu), 1);
-  tab.sync();
   __syncthreads();
-  // 3. gamma of the current colour, conflict mask, f = sum / 2
+  // 3. gamma of the current colour, its expiry kInf, f = sum / 2
   uint32_t fs = 0;
   for (int v = tid; v < n; v += BLOCK) {
     const uint32_t cv = cg[v];
     const uint32_t g = tab.gamma(v * kp + (int)cv);
+    tab.set_tabu(v * kp + (int)cv, Tab::kInf);
     cg[v] = cv | (g << 16);
-    if (g) atomicOr(&cmask[v >> 5], 1u << (v & 31));
     fs += g;
   }
   fs = wave_sum_u32(fs);
-  if (lane == 0) redc[wid] = fs;
+  if (lane == 0) red[wid].x = fs;
   __syncthreads();
   int f = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) f += (int)redc[w];
+  for (int w = 0; w < NW; ++w) f += (int)red[w].x;
   f >>= 1;
-  if (wid == 0) build_conflict_list(cmask, conf, sc, nwords, lane);
-  __syncthreads();
-  int C = sc[0];
+  rebuild();  // its barrier also retires the reads of red above
 
   int t = 0, f_best = f, base = 0;
   bool best_cur = true;
@@ -312,52 +416,65 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   uint64_t st_moves = 0, st_noops = 0, st_conf = 0, st_deg = 0, st_ties = 0, st_cap = 0;
   uint64_t fp = kFnvOffset;
   uint32_t Lreg = 0;
-  // quads (i, q): the i-th conflicting vertex, colours 4q..4q+3; thread tid takes quads tid + s*BLOCK
+  // quads (i, q): list entry i, colours 4q..4q+3; thread tid takes quads tid + s*BLOCK
   const int kq = kp >> 2;
   const int i0 = tid / kq, q0 = tid - (tid / kq) * kq, di = BLOCK / kq, dq = BLOCK - (BLOCK / kq) * kq;
+  auto step = [&](int& i, int& q) {
+    q += dq;
+    i += di;
+    if (q >= kq) {
+      q -= kq;
+      ++i;
+    }
+  };
 
   while (t < a.T && f > 0) {
+    int len = (int)sc[0], dead = (int)sc[1];
+    if (4 * dead > len || len > n + 32) {  // compact (every thread read sc before this barrier)
+      __syncthreads();
+      rebuild();
+      len = (int)sc[0];
+      dead = 0;
+    }
+    const int C = len - dead;  // conflicting vertices
     if (Tab::kRebase && t - base == kRebaseEvery) {
       for (int i = tid; i < nk; i += BLOCK) tab.rebase(i);
       base += kRebaseEvery;
-      tab.sync();
       __syncthreads();
     }
     const uint32_t trel = Tab::kRebase ? (uint32_t)(t - base) : (uint32_t)t;
-    const int asp = f_best - f - 1;  // aspiration: delta <= asp  <=>  f + delta < f_best
+    const uint32_t thr = Tab::free_thr(trel);
+    // aspiration: f + delta < f_best  <=>  delta + kBias <= f_best - f - 1 + kBias
+    const int aspb = f_best - f - 1 + kBias;
     const int par = (t & 1) * NW;
     if (wid == 0 && (t & 63) == 0)
       Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, a.key), (uint32_t)a.ten_rand);
 
-    // ---- scan
-    uint32_t bd = 0xffffffffu, bidx = 0xffffffffu, bcnt = 0, s0 = 0, s1 = 0;
-    auto consider = [&](int v, int c, uint32_t x, uint32_t g, uint32_t ex) {
-      const int d = (int)g - (int)(x >> 16);
-      if (c < k && c != (int)(x & 0xffffu) && (ex <= trel || d <= asp)) {
-        const uint32_t bdv = (uint32_t)(d + kBias);
-        const uint32_t idx = ((uint32_t)v << 16) | (uint32_t)c;
-        if (bdv < bd) {
-          bd = bdv;
-          bidx = idx;
-          bcnt = 1;
-          s0 = idx;
-        } else if (bdv == bd) {
-          bidx = min(bidx, idx);
-          if (bcnt == 1) s1 = idx;
-          ++bcnt;
-        }
-      }
+    // ---- scan: best admissible biased delta, how many candidates share it,
+    // and the first two of them (move index (v << 16) | c)
+    uint32_t bd = kNone, cnt = 0, s0 = 0, s1 = 0;
+    auto consider = [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+      const uint32_t bdv = g + boff;  // gamma[v][c] - gamma[v][col v] + kBias
+      const uint32_t b = (fr || (int)bdv <= aspb) ? bdv : kNone;
+      const bool lt = b < bd, eq = b == bd;
+      s1 = (eq && cnt == 1u) ? idx : s1;
+      cnt = lt ? 1u : cnt + (eq ? 1u : 0u);
+      s0 = lt ? idx : s0;
+      bd = lt ? b : bd;
     };
-    auto step = [&](int& i, int& q) {
-      q += dq;
-      i += di;
-      if (q >= kq) {
-        q -= kq;
-        ++i;
-      }
+    auto do_quad = [&](int i, int q, auto&& fn) {
+      const uint32_t e = list[i];
+      const uint32_t v = e & 0xffffu;
+      uint32_t g4[4];
+      bool f4[4];
+      tab.quad((int)__umul24(v, (uint32_t)kp) + 4 * q, thr, g4, f4);
+      const uint32_t boff = (uint32_t)kBias - (e >> 16);
+      const uint32_t idx = (v << 16) | (uint32_t)(4 * q);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fn(idx + r, g4[r], f4[r], boff);
     };
+    const int totq = len * kq;
     {
-      const int totq = C * kq;
       int i = i0, q = q0, j = tid;
       // two quads per round: their loads are independent and issue together
       for (; j + BLOCK < totq; j += 2 * BLOCK) {
@@ -365,45 +482,112 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         step(i, q);
         const int ib = i, qb = q;
         step(i, q);
-        const int va = conf[ia], vb = conf[ib];
-        const uint32_t xa = cg[va], xb = cg[vb];
-        uint32_t ga[4], ea[4], gb[4], eb[4];
-        tab.read4(va * kp + 4 * qa, ga, ea);
-        tab.read4(vb * kp + 4 * qb, gb, eb);
+        const uint32_t ea = list[ia], eb = list[ib];
+        const uint32_t va = ea & 0xffffu, vb = eb & 0xffffu;
+        uint32_t ga[4], gb[4];
+        bool fa[4], fb[4];
+        tab.quad((int)__umul24(va, (uint32_t)kp) + 4 * qa, thr, ga, fa);
+        tab.quad((int)__umul24(vb, (uint32_t)kp) + 4 * qb, thr, gb, fb);
+        const uint32_t oa = (uint32_t)kBias - (ea >> 16), ob = (uint32_t)kBias - (eb >> 16);
+        const uint32_t xa = (va << 16) | (uint32_t)(4 * qa), xb = (vb << 16) | (uint32_t)(4 * qb);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) consider(va, 4 * qa + r, xa, ga[r], ea[r]);
+        for (int r = 0; r < 4; ++r) consider(xa + r, ga[r], fa[r], oa);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) consider(vb, 4 * qb + r, xb, gb[r], eb[r]);
+        for (int r = 0; r < 4; ++r) consider(xb + r, gb[r], fb[r], ob);
       }
-      if (j < totq) {
-        const int v = conf[i];
-        const uint32_t x = cg[v];
-        uint32_t g4[4], e4[4];
-        tab.read4(v * kp + 4 * q, g4, e4);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) consider(v, 4 * q + r, x, g4[r], e4[r]);
+      if (j < totq) do_quad(i, q, consider);
+    }
+
+    // ---- wave result: smallest (biased delta, Philox word, v, c).  The
+    // moves tied at the wave's best delta are hashed now, before the
+    // cross-wave step, so one barrier settles the iteration.  They are first
+    // gathered in LDS (two per lane from registers, more by a rescan of the
+    // lane's quads) so that one Philox evaluation per lane covers up to 64.
+    const uint32_t wbd = wave_min_u32(bd);
+    uint64_t hk = ~0ull;
+    if (wbd != kNone) {
+      auto hkey = [&](uint32_t idx) -> uint64_t {
+        const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, a.key);
+        return ((uint64_t)h << 32) | idx;
+      };
+      auto is_tie = [&](uint32_t g, bool fr, uint32_t boff) {
+        const uint32_t bdv = g + boff;
+        return (fr || (int)bdv <= aspb) && bdv == wbd;
+      };
+      const bool tie = bd == wbd;
+      const bool A = tie && cnt <= 2u, B = tie && cnt == 2u, R = tie && cnt > 2u;
+      const uint64_t mA = __ballot(A), mB = __ballot(B);
+      const uint32_t nR = wave_sum_u32(R ? cnt : 0u);
+      const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
+      const uint32_t total = nA + nB + nR;
+      if (total <= (uint32_t)kStage) {
+        uint32_t* stg = stage + wid * (kStage + 4);
+        uint32_t* rctr = stg + kStage;
+        if (lane == 0) *rctr = nA + nB;
+        if (A) stg[__builtin_amdgcn_mbcnt_hi((uint32_t)(mA >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mA, 0u))] = s0;
+        if (B) stg[nA + __builtin_amdgcn_mbcnt_hi((uint32_t)(mB >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mB, 0u))] = s1;
+        if (R) {
+          uint32_t p = atomicAdd(rctr, cnt);
+          int i = i0, q = q0;
+          for (int j = tid; j < totq; j += BLOCK) {
+            do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+              if (is_tie(g, fr, boff)) stg[p++] = idx;
+            });
+            step(i, q);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t c0 = 0; c0 < total; c0 += kWave)
+          if (c0 + lane < total) hk = umin64(hk, hkey(stg[c0 + lane]));
+      } else {
+        // too many ties to stage: every lane hashes its own
+        if (A) hk = hkey(s0);
+        if (B) hk = umin64(hk, hkey(s1));
+        if (R) {
+          int i = i0, q = q0;
+          for (int j = tid; j < totq; j += BLOCK) {
+            do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+              if (is_tie(g, fr, boff)) hk = umin64(hk, hkey(idx));
+            });
+            step(i, q);
+          }
+        }
       }
     }
-    // ---- reduce: minimum (delta, v, c) and the number of moves at that delta
     {
-      const uint64_t wk = wave_min_u64(((uint64_t)bd << 32) | bidx);
-      const uint32_t wcnt = wave_sum_u32(bd == (uint32_t)(wk >> 32) ? bcnt : 0u);
-      if (lane == 0) {
-        red[par + wid] = wk;
-        redc[par + wid] = wcnt;
-      }
+      const uint64_t whk = wave_min_u64(hk);
+      const uint32_t wcnt = wave_sum_u32(bd == wbd ? cnt : 0u);
+      // colour of this wave's chosen vertex, read while no wave writes cg,
+      // and (byte gamma) whether the move would grow a class past 255
+      const uint32_t wold = wbd != kNone ? (cg[(uint32_t)whk >> 16] & 0xffffu) : 0u;
+      const uint32_t ovf = Tab::kBounded && wbd != kNone && csize[(uint32_t)whk & 0xffffu] >= 255u ? 1u : 0u;
+      if (lane == 0)
+        red[par + wid] = make_uint4((wbd & 0xffffu) | (wold << 16) | (ovf << 31), wcnt, (uint32_t)whk,
+                                    (uint32_t)(whk >> 32));
     }
     __syncthreads();
-    uint64_t gk = red[par];
+    // cross-wave: smallest (delta, hash, v, c); tie count over the waves at that delta
+    uint32_t bx, bz, bw, gcnt;
+    {
+      const uint4 e0 = red[par];
+      bx = e0.x; gcnt = e0.y; bz = e0.z; bw = e0.w;
+    }
 #pragma unroll
-    for (int w = 1; w < NW; ++w) gk = umin64(gk, red[par + w]);
-    const uint32_t gbd = (uint32_t)(gk >> 32);
-    uint32_t gcnt = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w)
-      if ((uint32_t)(red[par + w] >> 32) == gbd) gcnt += redc[par + w];
+    for (int w = 1; w < NW; ++w) {
+      const uint4 e = red[par + w];
+      const uint32_t eb = e.x & 0xffffu, bb = bx & 0xffffu;
+      const uint64_t eh = ((uint64_t)e.w << 32) | e.z, bh = ((uint64_t)bw << 32) | bz;
+      gcnt = eb < bb ? e.y : (eb == bb ? gcnt + e.y : gcnt);
+      const bool take = eb < bb || (eb == bb && eh < bh);
+      bx = take ? e.x : bx;
+      bz = take ? e.z : bz;
+      bw = take ? e.w : bw;
+    }
+    const uint32_t gbd = bx & 0xffffu;
 
-    if (gbd == 0xffffffffu) {  // nothing admissible: no-op iteration
+    if (gbd == 0xffffu) {  // nothing admissible: no-op iteration
       if (wid == 0) {
         ++st_noops;
         st_conf += (uint64_t)C;
@@ -418,108 +602,98 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       continue;
     }
 
-    uint32_t win;
-    if (gcnt == 1) {
-      win = (uint32_t)gk;
-    } else {
-      // ties on delta: smallest (Philox word, v, c) among the tied moves
-      uint64_t hk = ~0ull;
-      if (bd == gbd) {
-        auto hkey = [&](uint32_t idx) -> uint64_t {
-          const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, a.key);
-          return ((uint64_t)h << 32) | idx;
-        };
-        if (bcnt <= 2) {
-          hk = hkey(s0);
-          if (bcnt == 2) hk = umin64(hk, hkey(s1));
-        } else {
-          const int totq = C * kq;
-          const int dmin = (int)gbd - kBias;
-          int i = i0, q = q0;
-          for (int j = tid; j < totq; j += BLOCK) {
-            const int v = conf[i];
-            const uint32_t x = cg[v];
-            uint32_t g4[4], e4[4];
-            tab.read4(v * kp + 4 * q, g4, e4);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int c = 4 * q + r;
-              const int d = (int)g4[r] - (int)(x >> 16);
-              if (c < k && c != (int)(x & 0xffffu) && d == dmin && (e4[r] <= trel || d <= asp))
-                hk = umin64(hk, hkey(((uint32_t)v << 16) | (uint32_t)c));
-            }
-            step(i, q);
-          }
-        }
-      }
-      hk = wave_min_u64(hk);
-      if (lane == 0) red2[par + wid] = hk;
-      __syncthreads();
-      uint64_t gh = red2[par];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) gh = umin64(gh, red2[par + w]);
-      win = (uint32_t)gh;
+    if (Tab::kBounded && (bx >> 31)) {  // left to the 16-bit rerun
+      if (tid == 0) a.iters[li] = -2;
+      return;
     }
-
-    // ---- apply (wave 0)
-    const int vs = (int)(win >> 16), cs = (int)(win & 0xffffu);
+    // ---- apply: every thread takes a share of the neighbours of v*
+    const uint32_t win = bz;
+    const int vs = (int)(win >> 16), cs = (int)(win & 0xffffu), old = (int)((bx >> 16) & 0x7fffu);
     const int fnew = f + ((int)gbd - kBias);
     const bool snap = best_cur && fnew >= f_best;  // leaving the best state: keep a copy
-    if (wid == 0) {
-      if (snap)
-        for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffffu);
-      const int old = (int)(cg[vs] & 0xffffu);
-      const uint32_t Lt = readlane(Lreg, t & 63);
-      int64_t ttf = (int64_t)a.ten_num * fnew / a.ten_den;
-      const bool capped = ttf > kTenureCap;
-      if (capped) ttf = kTenureCap;
-      const int rs = rp[vs], re = rp[vs + 1];
-      auto update = [&](int u) {
-        const uint32_t xu = cg[u];
-        const int cu = (int)(xu & 0xffffu);
-        tab.add(u * kp + old, -1);
-        tab.add(u * kp + cs, +1);
-        if (cu == old) {
-          cg[u] = xu - 0x10000u;
-          if ((xu >> 16) == 1u) atomicAnd(&cmask[u >> 5], ~(1u << (u & 31)));
-        } else if (cu == cs) {
-          cg[u] = xu + 0x10000u;
-          if ((xu >> 16) == 0u) atomicOr(&cmask[u >> 5], 1u << (u & 31));
+    const int rs = rp[vs], re = rp[vs + 1];
+    if (wid == 0 && snap)
+      for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffffu);
+    {
+      // neighbour u: gamma[u][old] - 1, gamma[u][c*] + 1; if u has colour old
+      // or c*, its own gamma and its conflict-list entry follow
+      auto update = [&](int u, bool live) {
+        uint32_t xu = 0, gu = 0;
+        bool lo = false, hi = false;
+        if (live) {
+          xu = cg[u];
+          const uint32_t cu = xu & 0xffffu;
+          gu = xu >> 16;
+          tab.add(u * kp + old, -1);
+          tab.add(u * kp + cs, +1);
+          lo = cu == (uint32_t)old;
+          hi = cu == (uint32_t)cs;
+          cg[u] = xu - (lo ? 0x10000u : 0u) + (hi ? 0x10000u : 0u);
+          if ((lo && gu > 1u) || (hi && gu > 0u)) list[pos[u]] = ((hi ? gu + 1u : gu - 1u) << 16) | (uint32_t)u;
+          if (lo && gu == 1u) {
+            list[pos[u]] = kTomb;
+            pos[u] = kNoPos;
+          }
         }
+        const bool ins = hi && gu == 0u;
+        const uint32_t p = wave_append(&sc[0], ins, lane);
+        if (ins) {
+          list[p] = (1u << 16) | (uint32_t)u;
+          pos[u] = p;
+        }
+        (void)wave_append(&sc[1], lo && gu == 1u, lane);
       };
-      // the first 8 x 64 neighbours: all loads issued before any is used
-      constexpr int kPre = 8;
+      // the first kPre * BLOCK neighbours: all loads issued before any is used
+      constexpr int kPre = BLOCK >= 256 ? 2 : 4;
       int nb[kPre];
 #pragma unroll
       for (int r = 0; r < kPre; ++r) {
-        const int e = rs + lane + r * kWave;
+        const int e = rs + tid + r * BLOCK;
         nb[r] = e < re ? a.col_idx[e] : -1;
       }
 #pragma unroll
       for (int r = 0; r < kPre; ++r)
-        if (nb[r] >= 0) update(nb[r]);
-      for (int e = rs + kPre * kWave + lane; e < re; e += kWave) update(a.col_idx[e]);
+        if (rs + r * BLOCK < re) update(nb[r], nb[r] >= 0);  // uniform per round: ballots see the whole wave
+      for (int e0 = rs + kPre * BLOCK; e0 < re; e0 += BLOCK) {
+        const int e = e0 + tid;
+        update(e < re ? a.col_idx[e] : 0, e < re);
+      }
+    }
+    if (wid == 0) {
+      const uint32_t Lt = readlane(Lreg, t & 63);
+      const uint64_t prod = (uint64_t)(uint32_t)a.ten_num * (uint32_t)fnew;
+      uint32_t ttf = prod <= 0xffffffffull ? (uint32_t)prod / (uint32_t)a.ten_den
+                                           : (uint32_t)std::min<uint64_t>(prod / (uint32_t)a.ten_den, kTenureCap + 1);
+      const bool capped = ttf > (uint32_t)kTenureCap;
+      if (capped) ttf = kTenureCap;
       if (lane == 0) {
-        tab.set_tabu(vs * kp + old, trel + Lt + (uint32_t)ttf);
+        tab.set_tabu(vs * kp + old, trel + Lt + ttf);
+        tab.set_tabu(vs * kp + cs, Tab::kInf);
         const uint32_t gnew = tab.gamma(vs * kp + cs);
         cg[vs] = (uint32_t)cs | (gnew << 16);
-        if (gnew == 0u) atomicAnd(&cmask[vs >> 5], ~(1u << (vs & 31)));
+        if (Tab::kBounded) {
+          csize[old] -= 1u;
+          csize[cs] += 1u;
+        }
+        if (gnew == 0u) {
+          list[pos[vs]] = kTomb;
+          pos[vs] = kNoPos;
+          atomicAdd(&sc[1], 1u);
+        } else {
+          list[pos[vs]] = (gnew << 16) | (uint32_t)vs;
+        }
+        if (a.trace && t < a.trace_cap) {
+          int32_t* tr = a.trace + ((size_t)li * a.trace_cap + t) * 2;
+          tr[0] = vs | (cs << 16);
+          tr[1] = fnew;
+        }
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      build_conflict_list(cmask, conf, sc, nwords, lane);
       ++st_moves;
       st_conf += (uint64_t)C;
       st_deg += (uint64_t)(re - rs);
-      st_ties += gcnt > 1;
+      st_ties += gcnt > 1u;
       st_cap += capped;
       fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, fnew);
-      if (lane == 0 && a.trace && t < a.trace_cap) {
-        int32_t* tr = a.trace + ((size_t)li * a.trace_cap + t) * 2;
-        tr[0] = vs | (cs << 16);
-        tr[1] = fnew;
-      }
-      tab.sync();
     }
     f = fnew;
     if (f < f_best) {
@@ -530,7 +704,6 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     }
     ++t;
     __syncthreads();
-    C = sc[0];
   }
 
   if (wid == 0) {
@@ -554,6 +727,5 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     }
   }
 }
-
 
 }  // namespace dlm

@@ -31,27 +31,91 @@ __global__ __launch_bounds__(BLOCK) void tabucol_kernel(TabuArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int li = blockIdx.x;
   unsigned char* gtab =
-      a.gtab ? a.gtab + (size_t)li * (size_t)a.n * (size_t)tab_stride(a.k) * Tab::kGlobalBytes : nullptr;
+      a.gtab ? a.gtab + (size_t)li * (size_t)tab_entries(a.n, a.k) * Tab::kGlobalBytes : nullptr;
   tabu_individual<BLOCK, Tab>(a, li, gtab, smem);
 }
 
+// Byte-gamma runs that gave up (iters = -2: a colour class would pass 255
+// vertices) start again from their saved start colouring with the packed
+// 16-bit table in device memory.  A persistent grid walks the population;
+// every workgroup owns one table slot and skips the individuals that
+// finished.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void tabucol_rerun_kernel(TabuArgs a, const int16_t* __restrict__ start,
+                                                              unsigned char* __restrict__ slots, int32_t pop) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned char* slot = slots + (size_t)blockIdx.x * (size_t)tab_entries(a.n, a.k) * TabGlobal16::kGlobalBytes;
+  for (int li = blockIdx.x; li < pop; li += gridDim.x) {
+    if (a.iters[li] != -2) continue;
+    int16_t* gcol = a.colors + (size_t)li * a.n;
+    for (int v = threadIdx.x; v < a.n; v += BLOCK) gcol[v] = start[(size_t)li * a.n + v];
+    __syncthreads();
+    tabu_individual<BLOCK, TabGlobal16>(a, li, slot, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void copy_i16_kernel(const int16_t* __restrict__ src, int16_t* __restrict__ dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+struct Rerun {
+  const int16_t* start;
+  unsigned char* slots;
+  int32_t grid;
+};
+
 template <int BLOCK, class Tab>
-static int launch_block(const TabuArgs& a, int pop, size_t lds, hipStream_t s) {
-  auto kern = tabucol_kernel<BLOCK, Tab>;
-  DLM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kern, dim3(pop), dim3(BLOCK), lds, s, a);
+static int launch_block(const TabuArgs& a, int pop, size_t lds, hipStream_t s, const Rerun* rr) {
+  if (rr) {
+    auto kern = tabucol_rerun_kernel<BLOCK>;
+    DLM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(rr->grid), dim3(BLOCK), lds, s, a, rr->start, rr->slots, pop);
+  } else {
+    auto kern = tabucol_kernel<BLOCK, Tab>;
+    DLM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(pop), dim3(BLOCK), lds, s, a);
+  }
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }
 
+// resident workgroups per CU of the search kernel at this LDS size (0 if unknown)
+template <int BLOCK, class Tab>
+static int resident_b(size_t lds) {
+  int nb = 0;
+  auto kern = tabucol_kernel<BLOCK, Tab>;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
 template <class Tab>
-static int launch_tab(const TabuArgs& a, int pop, int block, size_t lds, hipStream_t s) {
+static int resident(int block, size_t lds) {
   switch (block) {
-    case 64: return launch_block<64, Tab>(a, pop, lds, s);
-    case 128: return launch_block<128, Tab>(a, pop, lds, s);
-    case 256: return launch_block<256, Tab>(a, pop, lds, s);
-    case 512: return launch_block<512, Tab>(a, pop, lds, s);
-    case 1024: return launch_block<1024, Tab>(a, pop, lds, s);
+    case 64: return resident_b<64, Tab>(lds);
+    case 128: return resident_b<128, Tab>(lds);
+    case 256: return resident_b<256, Tab>(lds);
+    case 512: return resident_b<512, Tab>(lds);
+    case 1024: return resident_b<1024, Tab>(lds);
+  }
+  return 0;
+}
+
+// rr != nullptr launches the 16-bit rerun pass instead of the search
+template <class Tab>
+static int launch_tab(const TabuArgs& a, int pop, int block, size_t lds, hipStream_t s,
+                      const Rerun* rr = nullptr) {
+  switch (block) {
+    case 64: return launch_block<64, Tab>(a, pop, lds, s, rr);
+    case 128: return launch_block<128, Tab>(a, pop, lds, s, rr);
+    case 256: return launch_block<256, Tab>(a, pop, lds, s, rr);
+    case 512: return launch_block<512, Tab>(a, pop, lds, s, rr);
+    case 1024: return launch_block<1024, Tab>(a, pop, lds, s, rr);
   }
   return set_error(DLM_E_INVAL, "dlm_tabu_batch: block=%d not in {64,128,256,512,1024}", block);
 }
@@ -84,15 +148,21 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
   const int n = g->n, k = p->k;
   const int64_t lds_max = device_lds_limit();
   int table = p->table;
-  if (table == DLM_TABLE_AUTO)
-    table = tabu_layout(n, k, nw, TabLds16::kLdsBytes).bytes <= (uint64_t)lds_max ? DLM_TABLE_LDS16
-                                                                                  : DLM_TABLE_GLOBAL16;
+  if (table == DLM_TABLE_AUTO) {
+    // the LDS tier that keeps more individuals resident per CU; byte gamma on a tie loses
+    const uint64_t l16 = tabu_layout(n, k, nw, TabLds16::kLdsBytes).bytes;
+    const uint64_t l8 = tabu_layout(n, k, nw, TabSplit8::kLdsBytes).bytes;
+    const int o16 = l16 <= (uint64_t)lds_max ? resident<TabLds16>(block, l16) : 0;
+    const int o8 = l8 <= (uint64_t)lds_max ? resident<TabSplit8>(block, l8) : 0;
+    table = o8 > o16 ? DLM_TABLE_SPLIT8 : (o16 > 0 ? DLM_TABLE_LDS16 : DLM_TABLE_GLOBAL16);
+  }
   int eb = 0, gb = 0;
   switch (table) {
     case DLM_TABLE_LDS16: eb = TabLds16::kLdsBytes; break;
     case DLM_TABLE_LDS32: eb = TabLds32::kLdsBytes; break;
     case DLM_TABLE_GLOBAL16: eb = 0; gb = TabGlobal16::kGlobalBytes; break;
     case DLM_TABLE_SPLIT16: eb = TabSplit16::kLdsBytes; gb = TabSplit16::kGlobalBytes; break;
+    case DLM_TABLE_SPLIT8: eb = TabSplit8::kLdsBytes; gb = TabSplit8::kGlobalBytes; break;
     default: return set_error(DLM_E_INVAL, "dlm_tabu_batch: unknown table %d", table);
   }
   const uint64_t lds = tabu_layout(n, k, nw, eb).bytes;
@@ -103,8 +173,40 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
              make_key(p->seed), n, k, p->max_iters, p->ten_num, p->ten_den, p->ten_rand,
              p->ind_base, p->trace_cap};
   hipStream_t s = (hipStream_t)stream;
+  if (table == DLM_TABLE_SPLIT8) {
+    // rerun slots: a few per CU, at most 1 GiB of packed tables
+    const uint64_t slot_bytes = tab_entries(n, k) * TabGlobal16::kGlobalBytes;
+    int64_t slots = std::min<int64_t>(pop, 2 * (int64_t)device_cu_count());
+    slots = std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)((1ull << 30) / std::max<uint64_t>(slot_bytes, 1))));
+    const size_t lds_rr = tabu_layout(n, k, nw, TabGlobal16::kLdsBytes).bytes;
+    const size_t bytes = (size_t)pop * tab_entries(n, k) * TabSplit8::kGlobalBytes;
+    const int64_t cells = (int64_t)pop * n;
+    int16_t* start = nullptr;
+    unsigned char* slot_mem = nullptr;
+    DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
+    hipError_t e = hipMallocAsync((void**)&start, sizeof(int16_t) * (size_t)cells, s);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&slot_mem, (size_t)slots * slot_bytes, s);
+    int rc = e == hipSuccess ? DLM_OK : hip_fail(e, "hipMallocAsync");
+    if (rc == DLM_OK) {
+      hipLaunchKernelGGL(copy_i16_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, colors, start,
+                         cells);
+      const hipError_t le = hipGetLastError();
+      if (le != hipSuccess) rc = hip_fail(le, "copy_i16_kernel");
+    }
+    if (rc == DLM_OK) rc = launch_tab<TabSplit8>(a, pop, block, lds, s);
+    const Rerun rr{start, slot_mem, (int32_t)slots};
+    if (rc == DLM_OK) rc = launch_tab<TabGlobal16>(a, pop, block, lds_rr, s, &rr);
+    const hipError_t e1 = slot_mem ? hipFreeAsync(slot_mem, s) : hipSuccess;
+    const hipError_t e2 = start ? hipFreeAsync(start, s) : hipSuccess;
+    const hipError_t e3 = hipFreeAsync(a.gtab, s);
+    if (rc != DLM_OK) return rc;
+    DLM_HIP(e1);
+    DLM_HIP(e2);
+    DLM_HIP(e3);
+    return DLM_OK;
+  }
   if (gb > 0) {
-    const size_t bytes = (size_t)pop * n * tab_stride(k) * gb;
+    const size_t bytes = (size_t)pop * tab_entries(n, k) * gb;
     DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
     int rc = table == DLM_TABLE_SPLIT16 ? launch_tab<TabSplit16>(a, pop, block, lds, s)
                                         : launch_tab<TabGlobal16>(a, pop, block, lds, s);

@@ -38,10 +38,11 @@ def make_jobs(dlm, specs, seed=5):
 
 SPECS = [("gnp", 120, 0.5, 14, 9, 1500), ("planted", 300, 0.5, 9, 5, 2500),
          ("gnp", 60, 0.3, 5, 13, 800), ("gnp", 600, 0.5, 90, 3, 1200),   # 600 x 90: split or device table
-         ("planted", 200, 0.6, 20, 6, 2000)]
+         ("planted", 200, 0.6, 20, 6, 2000),
+         ("gnp", 740, 0.012, 3, 4, 800)]   # k = 3: classes near 255, byte-table reruns
 
 
-@pytest.mark.parametrize("block,budget", [(256, 0), (64, 40000), (512, 80000)])
+@pytest.mark.parametrize("block,budget", [(256, 0), (64, 40000), (512, 80000), (128, 20000)])
 def test_multi_equals_single(dlm, dev, block, budget):
     jobs, starts = make_jobs(dlm, SPECS)
     say(f"multi plan block={block} budget={budget}")

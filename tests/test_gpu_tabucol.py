@@ -96,7 +96,7 @@ def test_parity_shapes(dlm, dev, shape, block):
     compare(gpu, ref, ids, f"n{n} k{k} block{block}")
 
 
-@pytest.mark.parametrize("table", ["lds16", "lds32", "global16", "split16"])
+@pytest.mark.parametrize("table", ["lds16", "lds32", "global16", "split16", "split8"])
 def test_parity_tables(dlm, dev, table):
     g = gnp(180, 0.5, seed=7)
     k, T, pop = 19, 20000, 6   # long enough to cross the 16-bit expiry rebase
@@ -200,3 +200,67 @@ def test_gnp500_split_table_sampled(dlm, dev):
     say("tabu gnp500 split16 pop=24 T=20000")
     gpu = gpu_run(dlm, g, starts, k, T, w.tabu_seed, table="split16", block=256)
     compare(gpu, ref, range(pop), "gnp500 split16")
+
+
+def test_gnp500_byte_table_sampled(dlm, dev):
+    """Byte gamma in LDS on the G(500, 0.5) shape: same results as the oracle."""
+    w = workload("gnp500")
+    g, k = w.graphs[0], w.k[0]
+    pop, T = 24, 20000
+    starts = oracle.init_random(g.n, k, pop, seed=w.init_seed)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=w.tabu_seed)
+    say("tabu gnp500 split8 pop=24 T=20000")
+    gpu = gpu_run(dlm, g, starts, k, T, w.tabu_seed, table="split8", block=256)
+    compare(gpu, ref, range(pop), "gnp500 split8")
+
+
+def _class_sizes_over_run(start, k, trace, iters):
+    """Largest class size reached along an oracle trajectory (start included)."""
+    col = start.astype(np.int64).copy()
+    size = np.bincount(col, minlength=k)
+    worst = [int(size.max())]
+    for t in range(iters):
+        rec = int(trace[t][0])
+        if rec < 0:
+            continue
+        v, c = rec & 0xffff, rec >> 16
+        size[col[v]] -= 1
+        size[c] += 1
+        col[v] = c
+        worst.append(int(size.max()))
+    return worst
+
+
+def test_byte_table_reruns_when_a_class_passes_255(dlm, dev):
+    """k = 3 on 740 vertices: classes of about 247.  Individuals whose start
+    already has a class above 255, and individuals whose class grows past 255
+    during the search, are both rerun with 16-bit gamma; every result must
+    equal the oracle's."""
+    g = gnp(740, 0.012, seed=11)
+    k, T, pop = 3, 1500, 12
+    starts = oracle.init_random(g.n, k, pop, seed=21)
+    ids = np.arange(pop)
+    ref = oracle.tabucol_batch(g, starts, ids, k, T, seed=5)
+    at_start, mid_run = 0, 0
+    for i in range(pop):
+        tr = oracle.tabucol(g, starts[i], k, T, seed=5, ind=i, trace_cap=T)
+        worst = _class_sizes_over_run(starts[i], k, tr["trace"], tr["iters"])
+        at_start += worst[0] > 255
+        mid_run += worst[0] <= 255 and max(worst) > 255
+    assert at_start > 0 and mid_run > 0, (at_start, mid_run)  # both paths are exercised
+    say(f"tabu split8 rerun n=740 k=3 ({at_start} at start, {mid_run} mid-run)")
+    gpu = gpu_run(dlm, g, starts, k, T, 5, table="split8", block=256)
+    compare(gpu, ref, ids, "split8 rerun")
+
+
+def test_gnp1000_k85_byte_table_and_auto(dlm, dev):
+    """G(1000, 0.5), k = 85 (the memetic shape, whose 16-bit table does not fit
+    LDS): the byte table and the automatic choice both equal the oracle."""
+    g = gnp(1000, 0.5, seed=0)
+    k, T, pop = 85, 4000, 6
+    starts = oracle.init_random(g.n, k, pop, seed=3)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=9)
+    for table in ("split8", "auto"):
+        say(f"tabu gnp1000 k=85 {table}")
+        gpu = gpu_run(dlm, g, starts, k, T, 9, table=table, block=256)
+        compare(gpu, ref, range(pop), f"gnp1000 {table}")
