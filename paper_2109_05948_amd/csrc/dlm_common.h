@@ -76,35 +76,33 @@ constexpr int kMirror = 0x140;     // row_mirror
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t x) {
-  return static_cast<uint32_t>(
-      __builtin_amdgcn_update_dpp(static_cast<int>(x), static_cast<int>(x), CTRL, 0xF, 0xF, false));
-}
-
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp_mov64(uint64_t x) {
-  const uint32_t lo = dpp_mov<CTRL>(static_cast<uint32_t>(x));
-  const uint32_t hi = dpp_mov<CTRL>(static_cast<uint32_t>(x >> 32));
-  return (static_cast<uint64_t>(hi) << 32) | lo;
+  // every control used here permutes lanes within a row, so no lane reads out
+  // of bounds; bound_ctrl lets the compiler fold the move into the consumer
+  // (one v_min_u32_dpp / v_add_u32_dpp per step)
+  return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), CTRL, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
   return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), lane));
 }
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
-  return (static_cast<uint64_t>(readlane(static_cast<uint32_t>(x >> 32), lane)) << 32) |
-         readlane(static_cast<uint32_t>(x), lane);
-}
-
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  x = min(x, dpp_mov<dpp::kXor1>(x));
+  x = min(x, dpp_mov<dpp::kXor2>(x));
+  x = min(x, dpp_mov<dpp::kHalfMirror>(x));
+  x = min(x, dpp_mov<dpp::kMirror>(x));
+  return min(min(readlane(x, 0), readlane(x, 16)), min(readlane(x, 32), readlane(x, 48)));
+}
+
+// smallest 64-bit key (hi, lo): the minimum of hi, then the minimum of lo
+// over the lanes holding that hi
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-  x = umin64(x, dpp_mov64<dpp::kXor1>(x));
-  x = umin64(x, dpp_mov64<dpp::kXor2>(x));
-  x = umin64(x, dpp_mov64<dpp::kHalfMirror>(x));
-  x = umin64(x, dpp_mov64<dpp::kMirror>(x));
-  return umin64(umin64(readlane64(x, 0), readlane64(x, 16)),
-                umin64(readlane64(x, 32), readlane64(x, 48)));
+  const uint32_t hi = static_cast<uint32_t>(x >> 32);
+  const uint32_t mh = wave_min_u32(hi);
+  const uint32_t ml = wave_min_u32(hi == mh ? static_cast<uint32_t>(x) : 0xffffffffu);
+  return (static_cast<uint64_t>(mh) << 32) | ml;
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
@@ -113,14 +111,6 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
   x += dpp_mov<dpp::kHalfMirror>(x);
   x += dpp_mov<dpp::kMirror>(x);
   return readlane(x, 0) + readlane(x, 16) + readlane(x, 32) + readlane(x, 48);
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-  x = min(x, dpp_mov<dpp::kXor1>(x));
-  x = min(x, dpp_mov<dpp::kXor2>(x));
-  x = min(x, dpp_mov<dpp::kHalfMirror>(x));
-  x = min(x, dpp_mov<dpp::kMirror>(x));
-  return min(min(readlane(x, 0), readlane(x, 16)), min(readlane(x, 32), readlane(x, 48)));
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {

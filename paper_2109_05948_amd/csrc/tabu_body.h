@@ -320,6 +320,20 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred, in
   return b + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// A copy of a uniform device-memory pointer in scalar registers of its own,
+// so that the argument block it came from (loaded as one 16-register tuple)
+// can die; typed as a global-address-space pointer so accesses stay global
+// (not flat) instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> own_sgpr(T* p) {
+  uint64_t x = reinterpret_cast<uint64_t>(p);
+  asm volatile("" : "+s"(x));
+  return (gptr<T>)x;
+}
+
 // One individual (row li of a.colors) searched by the calling workgroup.
 // gtab: the device-memory part of this workgroup's table (global and split tiers).
 //
@@ -335,6 +349,13 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const uint32_t ind = (uint32_t)(a.ind_base + li);
   const int n = a.n, k = a.k, kp = tab_stride(k), nk = (int)tab_entries(n, k);
+  // the fields the iteration loop needs, as separate values (the argument
+  // block as a whole would otherwise be kept in, and spilled from, scalar registers)
+  const gptr<const int32_t> col_idx = own_sgpr(a.col_idx);
+  const gptr<int32_t> trace = own_sgpr(a.trace);
+  const int trace_cap = a.trace_cap, T = a.T;
+  const Key key = a.key;
+  const uint32_t ten_num = (uint32_t)a.ten_num, ten_den = (uint32_t)a.ten_den, ten_rand = (uint32_t)a.ten_rand;
   const TabuLayout L = tabu_layout(n, k, NW, Tab::kLdsBytes);
   Tab tab = Tab::make(smem + L.tab, gtab);
   uint32_t* cg = reinterpret_cast<uint32_t*>(smem + L.cg);
@@ -412,9 +433,10 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
 
   int t = 0, f_best = f, base = 0;
   bool best_cur = true;
-  // statistics and fingerprint live in wave 0
-  uint64_t st_moves = 0, st_noops = 0, st_conf = 0, st_deg = 0, st_ties = 0, st_cap = 0;
-  uint64_t fp = kFnvOffset;
+  // statistics and fingerprint live in lane 0 of wave 0 (vector registers:
+  // the scalar file is the scarce one); moves = t - no-ops
+  uint64_t st_conf = 0, st_deg = 0, fp = kFnvOffset;
+  uint32_t st_noops = 0, st_ties = 0, st_cap = 0;
   uint32_t Lreg = 0;
   // quads (i, q): list entry i, colours 4q..4q+3; thread tid takes quads tid + s*BLOCK
   const int kq = kp >> 2;
@@ -428,7 +450,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     }
   };
 
-  while (t < a.T && f > 0) {
+  while (t < T && f > 0) {
     int len = (int)sc[0], dead = (int)sc[1];
     if (4 * dead > len || len > n + 32) {  // compact (every thread read sc before this barrier)
       __syncthreads();
@@ -448,7 +470,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     const int aspb = f_best - f - 1 + kBias;
     const int par = (t & 1) * NW;
     if (wid == 0 && (t & 63) == 0)
-      Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, a.key), (uint32_t)a.ten_rand);
+      Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, key), ten_rand);
 
     // ---- scan: best admissible biased delta, how many candidates share it,
     // and the first two of them (move index (v << 16) | c)
@@ -507,7 +529,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     uint64_t hk = ~0ull;
     if (wbd != kNone) {
       auto hkey = [&](uint32_t idx) -> uint64_t {
-        const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, a.key);
+        const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key);
         return ((uint64_t)h << 32) | idx;
       };
       auto is_tie = [&](uint32_t g, bool fr, uint32_t boff) {
@@ -568,32 +590,35 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
                                     (uint32_t)(whk >> 32));
     }
     __syncthreads();
-    // cross-wave: smallest (delta, hash, v, c); tie count over the waves at that delta
+    // cross-wave: smallest (delta, hash, v, c); tie count over the waves at
+    // that delta.  The slots are uniform: fold them in scalar registers.
+    auto rfl = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
     uint32_t bx, bz, bw, gcnt;
     {
       const uint4 e0 = red[par];
-      bx = e0.x; gcnt = e0.y; bz = e0.z; bw = e0.w;
+      bx = rfl(e0.x); gcnt = rfl(e0.y); bz = rfl(e0.z); bw = rfl(e0.w);
     }
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
       const uint4 e = red[par + w];
-      const uint32_t eb = e.x & 0xffffu, bb = bx & 0xffffu;
-      const uint64_t eh = ((uint64_t)e.w << 32) | e.z, bh = ((uint64_t)bw << 32) | bz;
-      gcnt = eb < bb ? e.y : (eb == bb ? gcnt + e.y : gcnt);
-      const bool take = eb < bb || (eb == bb && eh < bh);
-      bx = take ? e.x : bx;
-      bz = take ? e.z : bz;
-      bw = take ? e.w : bw;
+      const uint32_t ex = rfl(e.x), ey = rfl(e.y), ez = rfl(e.z), ew = rfl(e.w);
+      const uint32_t eb = ex & 0xffffu, bb = bx & 0xffffu;
+      const bool hless = ew < bw || (ew == bw && ez < bz);
+      gcnt = eb < bb ? ey : (eb == bb ? gcnt + ey : gcnt);
+      const bool take = eb < bb || (eb == bb && hless);
+      bx = take ? ex : bx;
+      bz = take ? ez : bz;
+      bw = take ? ew : bw;
     }
     const uint32_t gbd = bx & 0xffffu;
 
     if (gbd == 0xffffu) {  // nothing admissible: no-op iteration
-      if (wid == 0) {
+      if (wid == 0 && lane == 0) {
         ++st_noops;
         st_conf += (uint64_t)C;
         fp = fnv_step(fp, 0xffffu, 0xffffu, f);
-        if (lane == 0 && a.trace && t < a.trace_cap) {
-          int32_t* tr = a.trace + ((size_t)li * a.trace_cap + t) * 2;
+        if (trace && t < trace_cap) {
+          gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
           tr[0] = -1;
           tr[1] = f;
         }
@@ -649,24 +674,25 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
 #pragma unroll
       for (int r = 0; r < kPre; ++r) {
         const int e = rs + tid + r * BLOCK;
-        nb[r] = e < re ? a.col_idx[e] : -1;
+        nb[r] = e < re ? col_idx[e] : -1;
       }
 #pragma unroll
       for (int r = 0; r < kPre; ++r)
         if (rs + r * BLOCK < re) update(nb[r], nb[r] >= 0);  // uniform per round: ballots see the whole wave
       for (int e0 = rs + kPre * BLOCK; e0 < re; e0 += BLOCK) {
         const int e = e0 + tid;
-        update(e < re ? a.col_idx[e] : 0, e < re);
+        update(e < re ? col_idx[e] : 0, e < re);
       }
     }
     if (wid == 0) {
       const uint32_t Lt = readlane(Lreg, t & 63);
-      const uint64_t prod = (uint64_t)(uint32_t)a.ten_num * (uint32_t)fnew;
-      uint32_t ttf = prod <= 0xffffffffull ? (uint32_t)prod / (uint32_t)a.ten_den
-                                           : (uint32_t)std::min<uint64_t>(prod / (uint32_t)a.ten_den, kTenureCap + 1);
-      const bool capped = ttf > (uint32_t)kTenureCap;
-      if (capped) ttf = kTenureCap;
       if (lane == 0) {
+        // tenure term floor(num * f / den), capped; the product fits 32 bits in practice
+        const uint64_t prod = (uint64_t)ten_num * (uint32_t)fnew;
+        uint32_t ttf = prod <= 0xffffffffull ? (uint32_t)prod / ten_den
+                                             : (uint32_t)std::min<uint64_t>(prod / ten_den, kTenureCap + 1);
+        const bool capped = ttf > (uint32_t)kTenureCap;
+        if (capped) ttf = kTenureCap;
         tab.set_tabu(vs * kp + old, trel + Lt + ttf);
         tab.set_tabu(vs * kp + cs, Tab::kInf);
         const uint32_t gnew = tab.gamma(vs * kp + cs);
@@ -682,18 +708,17 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         } else {
           list[pos[vs]] = (gnew << 16) | (uint32_t)vs;
         }
-        if (a.trace && t < a.trace_cap) {
-          int32_t* tr = a.trace + ((size_t)li * a.trace_cap + t) * 2;
+        if (trace && t < trace_cap) {
+          gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
           tr[0] = vs | (cs << 16);
           tr[1] = fnew;
         }
+        st_conf += (uint64_t)C;
+        st_deg += (uint64_t)(re - rs);
+        st_ties += gcnt > 1u;
+        st_cap += capped;
+        fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, fnew);
       }
-      ++st_moves;
-      st_conf += (uint64_t)C;
-      st_deg += (uint64_t)(re - rs);
-      st_ties += gcnt > 1u;
-      st_cap += capped;
-      fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, fnew);
     }
     f = fnew;
     if (f < f_best) {
@@ -714,7 +739,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       a.iters[li] = t;
       if (a.stats) {
         int64_t* s = a.stats + (size_t)li * DLM_NSTATS;
-        s[0] = (int64_t)st_moves;
+        s[0] = (int64_t)(t - (int)st_noops);
         s[1] = (int64_t)st_noops;
         s[2] = (int64_t)st_conf;
         s[3] = (int64_t)st_deg;
