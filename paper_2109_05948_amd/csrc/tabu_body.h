@@ -28,9 +28,10 @@ constexpr int kStage = 128;              // tied moves a wave hashes in one stag
 // never read (the move rule excludes c = col v).
 
 // ---------------------------------------------------------------------------
-// Table storage policies.  quad(i, thr, g, fr) reads the four entries i..i+3
-// (i a multiple of 4) and reports gamma and "not tabu" (expiry <= trel, with
-// thr = free_thr(trel)).
+// Table storage policies.  load4(i) fetches the four entries i..i+3 (i a
+// multiple of 4) and eval4(raw, thr, g, fr) reports their gamma and "not
+// tabu" (expiry <= trel, with thr = free_thr(trel)); the two halves are
+// separate so that a thread can have several quads in flight.
 struct TabLds16 {
   static constexpr bool kBounded = false;
   static constexpr bool kRebase = true;
@@ -46,8 +47,9 @@ struct TabLds16 {
   __device__ __forceinline__ uint32_t gamma(int i) const { return w[i] & 0xffffu; }
   // expiry <= trel  <=>  the packed word <= (trel << 16) | 0xffff
   __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return (trel << 16) | 0xffffu; }
-  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
-    const uint4 x = *reinterpret_cast<const uint4*>(w + i);
+  using Raw = uint4;
+  __device__ __forceinline__ Raw load4(int i) const { return *reinterpret_cast<const uint4*>(w + i); }
+  __device__ static __forceinline__ void eval4(const Raw& x, uint32_t thr, uint32_t g[4], bool fr[4]) {
     g[0] = x.x & 0xffffu; fr[0] = x.x <= thr;
     g[1] = x.y & 0xffffu; fr[1] = x.y <= thr;
     g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
@@ -81,11 +83,15 @@ struct TabLds32 {
   __device__ __forceinline__ void add(int i, int d) { atomicAdd(&w[2 * i], (uint32_t)d); }
   __device__ __forceinline__ uint32_t gamma(int i) const { return w[2 * i]; }
   __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
-  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
-    const uint4 x = *reinterpret_cast<const uint4*>(w + 2 * i);
-    const uint4 y = *reinterpret_cast<const uint4*>(w + 2 * i + 4);
-    g[0] = x.x; fr[0] = x.y <= thr; g[1] = x.z; fr[1] = x.w <= thr;
-    g[2] = y.x; fr[2] = y.y <= thr; g[3] = y.z; fr[3] = y.w <= thr;
+  struct Raw {
+    uint4 x, y;
+  };
+  __device__ __forceinline__ Raw load4(int i) const {
+    return Raw{*reinterpret_cast<const uint4*>(w + 2 * i), *reinterpret_cast<const uint4*>(w + 2 * i + 4)};
+  }
+  __device__ static __forceinline__ void eval4(const Raw& r, uint32_t thr, uint32_t g[4], bool fr[4]) {
+    g[0] = r.x.x; fr[0] = r.x.y <= thr; g[1] = r.x.z; fr[1] = r.x.w <= thr;
+    g[2] = r.y.x; fr[2] = r.y.y <= thr; g[3] = r.y.z; fr[3] = r.y.w <= thr;
   }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { w[2 * i + 1] = ex; }
   __device__ __forceinline__ void rebase(int) {}
@@ -114,8 +120,9 @@ struct TabGlobal16 {
   }
   __device__ __forceinline__ uint32_t gamma(int i) const { return ld(i) & 0xffffu; }
   __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return (trel << 16) | 0xffffu; }
-  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t g[4], bool fr[4]) const {
-    const uint4 x = *reinterpret_cast<const uint4*>(w + i);
+  using Raw = uint4;
+  __device__ __forceinline__ Raw load4(int i) const { return *reinterpret_cast<const uint4*>(w + i); }
+  __device__ static __forceinline__ void eval4(const Raw& x, uint32_t thr, uint32_t g[4], bool fr[4]) {
     g[0] = x.x & 0xffffu; fr[0] = x.x <= thr;
     g[1] = x.y & 0xffffu; fr[1] = x.y <= thr;
     g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
@@ -160,9 +167,16 @@ struct TabSplit16 {
   __device__ __forceinline__ uint32_t gamma(int i) const { return g[i]; }
   __device__ __forceinline__ uint32_t ldt(int i) const { return tb[i]; }
   __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
-  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t gg[4], bool fr[4]) const {
-    const uint2 x = *reinterpret_cast<const uint2*>(g + i);
-    const uint64_t t = *reinterpret_cast<const uint64_t*>(tb + i);
+  struct Raw {
+    uint2 x;
+    uint64_t t;
+  };
+  __device__ __forceinline__ Raw load4(int i) const {
+    return Raw{*reinterpret_cast<const uint2*>(g + i), *reinterpret_cast<const uint64_t*>(tb + i)};
+  }
+  __device__ static __forceinline__ void eval4(const Raw& r, uint32_t thr, uint32_t gg[4], bool fr[4]) {
+    const uint2 x = r.x;
+    const uint64_t t = r.t;
     gg[0] = x.x & 0xffffu; gg[1] = x.x >> 16; gg[2] = x.y & 0xffffu; gg[3] = x.y >> 16;
     fr[0] = ((uint32_t)t & 0xffffu) <= thr;
     fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
@@ -209,9 +223,16 @@ struct TabSplit8 {
   }
   __device__ __forceinline__ uint32_t gamma(int i) const { return g[i]; }
   __device__ static __forceinline__ uint32_t free_thr(uint32_t trel) { return trel; }
-  __device__ __forceinline__ void quad(int i, uint32_t thr, uint32_t gg[4], bool fr[4]) const {
-    const uint32_t x = *reinterpret_cast<const uint32_t*>(g + i);
-    const uint64_t t = *reinterpret_cast<const uint64_t*>(tb + i);
+  struct Raw {
+    uint32_t x;
+    uint64_t t;
+  };
+  __device__ __forceinline__ Raw load4(int i) const {
+    return Raw{*reinterpret_cast<const uint32_t*>(g + i), *reinterpret_cast<const uint64_t*>(tb + i)};
+  }
+  __device__ static __forceinline__ void eval4(const Raw& r, uint32_t thr, uint32_t gg[4], bool fr[4]) {
+    const uint32_t x = r.x;
+    const uint64_t t = r.t;
     gg[0] = x & 0xffu; gg[1] = (x >> 8) & 0xffu; gg[2] = (x >> 16) & 0xffu; gg[3] = x >> 24;
     fr[0] = ((uint32_t)t & 0xffffu) <= thr;
     fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
@@ -489,7 +510,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       const uint32_t v = e & 0xffffu;
       uint32_t g4[4];
       bool f4[4];
-      tab.quad((int)__umul24(v, (uint32_t)kp) + 4 * q, thr, g4, f4);
+      Tab::eval4(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), thr, g4, f4);
       const uint32_t boff = (uint32_t)kBias - (e >> 16);
       const uint32_t idx = (v << 16) | (uint32_t)(4 * q);
 #pragma unroll
@@ -506,10 +527,12 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         step(i, q);
         const uint32_t ea = list[ia], eb = list[ib];
         const uint32_t va = ea & 0xffffu, vb = eb & 0xffffu;
+        const typename Tab::Raw ra = tab.load4((int)__umul24(va, (uint32_t)kp) + 4 * qa);
+        const typename Tab::Raw rb = tab.load4((int)__umul24(vb, (uint32_t)kp) + 4 * qb);
         uint32_t ga[4], gb[4];
         bool fa[4], fb[4];
-        tab.quad((int)__umul24(va, (uint32_t)kp) + 4 * qa, thr, ga, fa);
-        tab.quad((int)__umul24(vb, (uint32_t)kp) + 4 * qb, thr, gb, fb);
+        Tab::eval4(ra, thr, ga, fa);
+        Tab::eval4(rb, thr, gb, fb);
         const uint32_t oa = (uint32_t)kBias - (ea >> 16), ob = (uint32_t)kBias - (eb >> 16);
         const uint32_t xa = (va << 16) | (uint32_t)(4 * qa), xb = (vb << 16) | (uint32_t)(4 * qb);
 #pragma unroll
