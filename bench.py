@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
-                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000"])
+                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer"])
     ap.add_argument("--cutoff", type=float, default=300.0,
                     help="memetic1000: wall-clock limit per loop (seconds)")
     ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
@@ -148,6 +148,8 @@ def main():
     import paper_2109_05948_amd as dlm
     from workloads import workload
 
+    if args.workload == "scorer":
+        return bench_scorer(args, workload("memetic1000"), dlm, torch)
     w = workload(args.workload)
     if args.workload == "uneven64":
         return bench_uneven(args, w, dlm, torch)
@@ -341,6 +343,65 @@ def bench_memetic(args, w, dlm, torch):
                       "keep_frac": e["keep_frac"], "iters_per_tabu": T, "cutoff_s": args.cutoff,
                       "seeds": seeds},
            "loops": res}
+    print(json.dumps(out), flush=True)
+
+
+def bench_scorer(args, w, dlm, torch):
+    """The offspring scorer at the memetic shape (G(1000, 0.5), k = 85): score
+    the 32,768 GPX offspring of one generation, then train on 8,192 (start,
+    result) pairs for 5 epochs at batch 1024.  Inputs are random colourings
+    and standardised-normal targets, resident before timing.
+
+    Per colouring, inference gathers one FP32 W1 row (H1 = 256 floats) per
+    vertex and runs kpad x 256 x 128 BF16 MFMA products (kpad = k rounded up
+    to 32); training adds the two backward products (dH1, dW2) and the dW1
+    scatter, so about 3x the MFMA work and 2x the gather bytes."""
+    from workloads.scorer_init import scorer_weights
+    g, k = w.graphs[0], w.k[0]
+    n, h1, h2 = g.n, 256, 128
+    kpad = (k + 31) // 32 * 32
+    G = dlm.Graph.from_csr(g)
+    nchild, npairs, batch, epochs = 32768, 8192, 1024, 5
+    sc = dlm.Scorer(n, k, scorer_weights(n, seed=0), max_batch=batch)
+    col, _ = dlm.init_population(G, k, nchild, seed=5)
+    gen = torch.Generator().manual_seed(11)
+    tgt = torch.randn(npairs, generator=gen).to("cuda")
+    scores = torch.empty(nchild, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sc.score(col, out=scores)
+        sc.train(col[:npairs], tgt, batch, epochs)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        ev[s_][0].record(stream)
+        sc.score(col, out=scores)
+        ev[s_][1].record(stream)
+        sc.train(col[:npairs], tgt, batch, epochs)
+        ev[s_][2].record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    tr_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    gather_b = float(nchild) * n * h1 * 4
+    mfma_f = float(nchild) * 2 * kpad * h1 * h2
+    inf_gbs = gather_b / (inf_ms * 1e-3) / 1e9
+    tr_tflops = 3 * float(npairs * epochs) * 2 * kpad * h1 * h2 / (tr_ms * 1e-3) / 1e12
+    out = {"metric": "offspring scored/s (learned selection, memetic shape)", "value": nchild / (inf_ms * 1e-3),
+           "unit": "colourings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
+           "config": {"workload": "scorer", "graph": "G(n=1000, p=0.5) seed 0", "k": k,
+                      "offspring": nchild, "train_pairs": npairs, "batch": batch, "epochs": epochs},
+           "inference_ms": inf_ms, "train_ms": tr_ms,
+           "train_pairs_per_s": npairs * epochs / (tr_ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": inf_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": inf_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "scorer_fwd_kernel",
+                        "note": "W1 rows gathered per colouring (L2-resident, 1 MB)"},
+           "roofline_mfma": {"bound": "mfma", "achieved": mfma_f / (inf_ms * 1e-3) / 1e12, "peak": 2500.0,
+                             "unit": "TFLOP/s", "frac": mfma_f / (inf_ms * 1e-3) / 1e12 / 2500.0,
+                             "train_achieved": tr_tflops}}
     print(json.dumps(out), flush=True)
 
 

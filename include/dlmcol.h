@@ -235,8 +235,9 @@ int dlm_multi_autotune(const dlm_multi_item* items, int32_t count, int32_t calib
  *                  2 sum deg(v*), 3 tie iterations, 4 rounds whose best-g
  *                  state is legal, 5 final phi
  *   hash_dev       uint64[pop] or NULL: FNV-1a over (v, c, g >> shift)
- * Needs a weighted graph.  Errors: DLM_E_INVAL, DLM_E_UNSUPPORTED (LDS),
- * DLM_E_HIP.
+ * Needs a weighted graph with (2 max_w) << shift <= 2^30, so that every phi
+ * fits 31 bits.  Errors: DLM_E_INVAL, DLM_E_UNSUPPORTED (LDS, or weights too
+ * large for the shift), DLM_E_HIP.
  * ---------------------------------------------------------------------- */
 typedef struct dlm_wvcp_params {
   int32_t k;               /* colours available, 1..32767 */

@@ -13,14 +13,23 @@
 // state with a fresh freeze list; the iteration counter t runs on across
 // rounds.  The result is the best legal colouring met anywhere.
 //
-// LDS per individual: gamma[v][c] (u16), colour|gamma-of-own-colour per
-// vertex, weights, freeze expiries, best-g colouring, per-class (largest
-// weight, its multiplicity, second largest weight).
+// One iteration: a branch-free scan of every (v, c) one-move, a quad of
+// colours at a time with the per-vertex terms computed once per quad; each
+// wave hashes the moves tied at its best key before one barrier picks the
+// (key, hash, v, c) minimum; every thread takes a share of v*'s neighbours;
+// the class c* gains v* in O(1) and the class it left is rescanned only when
+// v* carried its largest weight alone or its second largest weight.
+//
+// LDS per individual: gamma[v][c] (u16, rows padded to 4 colours), per
+// vertex {colour | gamma of own colour, weight, frozen-until}, per class
+// (largest weight, its multiplicity, second largest weight), the best-g
+// colouring.
 #include "dlm_common.h"
 
 namespace dlm {
 
 constexpr uint64_t kGBias = 1ull << 62;
+constexpr int kWStage = 128;  // tied moves a wave hashes in one staged pass
 
 struct WvcpArgs {
   const int32_t* row_ptr;
@@ -35,31 +44,34 @@ struct WvcpArgs {
   int32_t n, k, T, R, ten_rand, frz, shift, ind_base, max_w;
 };
 
+// gamma rows are padded to kp = k rounded up to 4 colours (one 8-byte read
+// per quad of candidates); per vertex {colour | gamma(own colour) << 16,
+// weight, frozen-until, 0}; per class {largest weight, its multiplicity,
+// second largest, 0} and the largest weights again as a dense vector.
 struct WvcpLayout {
-  uint32_t gam, cg, w, frozen, bestg, m1, c1, m2, red, bytes;
+  uint32_t gam, vinfo, cls, m1v, bestg, red, stage, bytes;
 };
+
+__host__ __device__ constexpr int wvcp_stride(int k) { return (k + 3) & ~3; }
 
 __host__ __device__ inline WvcpLayout wvcp_layout(int n, int k, int nw) {
   WvcpLayout L;
+  const uint32_t kp = (uint32_t)wvcp_stride(k);
   uint32_t o = 0;
   L.gam = o;
-  o += align16(2u * n * k);
-  L.cg = o;
-  o += align16(4u * n);
-  L.w = o;
-  o += align16(4u * n);
-  L.frozen = o;
-  o += align16(4u * n);
+  o += align16(2u * n * kp);
+  L.vinfo = o;
+  o += 16u * n;
+  L.cls = o;
+  o += 16u * kp;
+  L.m1v = o;
+  o += align16(4u * kp);
   L.bestg = o;
   o += align16(2u * n);
-  L.m1 = o;
-  o += align16(4u * k);
-  L.c1 = o;
-  o += align16(4u * k);
-  L.m2 = o;
-  o += align16(4u * k);
   L.red = o;
-  o += 2u * 8u * 4u * nw;  // two parity buffers of {key, idx|cnt, hash} per wave
+  o += 2u * 32u * nw;  // two parity buffers of 8 words per wave
+  L.stage = o;
+  o += nw * 4u * (kWStage + 4);
   L.bytes = o;
   return L;
 }
@@ -96,28 +108,25 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int li = blockIdx.x;
   const uint32_t ind = (uint32_t)(a.ind_base + li);
-  const int n = a.n, k = a.k, nk = n * k, S = a.shift;
+  const int n = a.n, k = a.k, kp = wvcp_stride(k), kq = kp >> 2, S = a.shift;
   const WvcpLayout L = wvcp_layout(n, k, NW);
   uint16_t* gam = reinterpret_cast<uint16_t*>(smem + L.gam);
-  uint32_t* cg = reinterpret_cast<uint32_t*>(smem + L.cg);
-  int32_t* w = reinterpret_cast<int32_t*>(smem + L.w);
-  int32_t* frozen = reinterpret_cast<int32_t*>(smem + L.frozen);
+  uint4* vinfo = reinterpret_cast<uint4*>(smem + L.vinfo);  // {cg, weight, frozen, 0}
+  uint4* cls = reinterpret_cast<uint4*>(smem + L.cls);      // {m1, c1, m2, 0}
+  uint32_t* m1v = reinterpret_cast<uint32_t*>(smem + L.m1v);
   int16_t* bestg = reinterpret_cast<int16_t*>(smem + L.bestg);
-  uint32_t* m1 = reinterpret_cast<uint32_t*>(smem + L.m1);
-  uint32_t* c1 = reinterpret_cast<uint32_t*>(smem + L.c1);
-  uint32_t* m2 = reinterpret_cast<uint32_t*>(smem + L.m2);
-  uint64_t* rkey = reinterpret_cast<uint64_t*>(smem + L.red);  // [2][NW]
-  uint64_t* rhash = rkey + 2 * NW;                              // [2][NW]
-  uint32_t* ridx = reinterpret_cast<uint32_t*>(rhash + 2 * NW); // [2][NW]
-  uint32_t* rcnt = ridx + 2 * NW;                               // [2][NW]
+  uint32_t* red = reinterpret_cast<uint32_t*>(smem + L.red);  // [2][NW][8]
+  uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);
   int16_t* gcol = a.colors + (size_t)li * n;
+  const Key key = a.key;
+  const int32_t* __restrict__ col_idx = a.col_idx;
+  __shared__ int32_t s_red[2 * NW];
 
   int bad = 0;
   for (int v = tid; v < n; v += BLOCK) {
     const int c = gcol[v];
     bad |= (c < 0) | (c >= k);
     bestg[v] = (int16_t)c;
-    w[v] = a.weights[v];
   }
   if (__syncthreads_or(bad)) {
     if (tid == 0) a.best_legal[li] = -1;
@@ -128,46 +137,55 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
   int64_t phi = ((int64_t)k * a.max_w << S) / (2 * (int64_t)n);
   int64_t best_legal = INT64_MAX;
   int t = 0;
-  uint64_t st_moves = 0, st_noops = 0, st_deg = 0, st_ties = 0, st_legal_rounds = 0;
-  uint64_t fp = kFnvOffset;
+  // statistics and fingerprint live in lane 0 of wave 0; moves = t - no-ops
+  uint64_t st_deg = 0, fp = kFnvOffset;
+  uint32_t st_noops = 0, st_ties = 0, st_legal_rounds = 0;
   uint32_t Lreg = 0;
-  int Lbase = -64;
-  const int i0 = tid / k, c0 = tid - (tid / k) * k, di = BLOCK / k, dc = BLOCK - (BLOCK / k) * k;
-  __shared__ int32_t s_red[2 * NW];
-  __shared__ int32_t s_dcs;
+  const int i0 = tid / kq, q0 = tid - (tid / kq) * kq, di = BLOCK / kq, dq = BLOCK - (BLOCK / kq) * kq;
+  const int totq = n * kq;
+  auto step = [&](int& i, int& q) {
+    q += dq;
+    i += di;
+    if (q >= kq) {
+      q -= kq;
+      ++i;
+    }
+  };
 
   for (int r = 0; r < a.R; ++r) {
     if (r == a.R - 1) phi = (int64_t)(2 * a.max_w) << S;
+    const int32_t phi32 = (int32_t)phi;  // phi <= 2^30
     // ---- fresh round state from the best-g colouring of the previous round
-    for (int i = tid; i < nk; i += BLOCK) gam[i] = 0;
-    for (int v = tid; v < n; v += BLOCK) {
-      cg[v] = (uint32_t)(uint16_t)bestg[v];
-      frozen[v] = 0;
-    }
-    for (int c = tid; c < k; c += BLOCK) {
-      m1[c] = 0;
-      c1[c] = 0;
-      m2[c] = 0;
+    for (int i = tid; i < n * kp / 2; i += BLOCK) reinterpret_cast<uint32_t*>(gam)[i] = 0u;
+    for (int v = tid; v < n; v += BLOCK)
+      vinfo[v] = make_uint4((uint32_t)(uint16_t)bestg[v], (uint32_t)a.weights[v], 0u, 0u);
+    for (int c = tid; c < kp; c += BLOCK) {
+      cls[c] = make_uint4(0u, 0u, 0u, 0u);
+      m1v[c] = 0u;
     }
     __syncthreads();
     const int nnz = a.row_ptr[n];
-    for (int e = tid; e < nnz; e += BLOCK)
-      atomicAdd(reinterpret_cast<uint32_t*>(gam) + ((a.erow[e] * k + (int)(cg[a.col_idx[e]] & 0xffffu)) >> 1),
-                (a.erow[e] * k + (int)(cg[a.col_idx[e]] & 0xffffu)) & 1 ? 0x10000u : 1u);
-    for (int v = tid; v < n; v += BLOCK) atomicMax(&m1[cg[v] & 0xffffu], (uint32_t)w[v]);
+    for (int e = tid; e < nnz; e += BLOCK) {
+      const int ix = a.erow[e] * kp + (int)(vinfo[col_idx[e]].x & 0xffffu);
+      atomicAdd(reinterpret_cast<uint32_t*>(gam) + (ix >> 1), (ix & 1) ? 0x10000u : 1u);
+    }
+    for (int v = tid; v < n; v += BLOCK) atomicMax(&cls[vinfo[v].x & 0xffffu].x, vinfo[v].y);
     __syncthreads();
     uint32_t cs2 = 0;
     for (int v = tid; v < n; v += BLOCK) {
-      const uint32_t c = cg[v] & 0xffffu;
-      const uint32_t g = gam[v * k + (int)c];
-      cg[v] = c | (g << 16);
+      const uint32_t c = vinfo[v].x & 0xffffu, wv = vinfo[v].y;
+      const uint32_t g = gam[v * kp + (int)c];
+      vinfo[v].x = c | (g << 16);
       cs2 += g;
-      if ((uint32_t)w[v] == m1[c]) atomicAdd(&c1[c], 1u);
-      else atomicMax(&m2[c], (uint32_t)w[v]);
+      if (wv == cls[c].x) atomicAdd(&cls[c].y, 1u);
+      else atomicMax(&cls[c].z, wv);
     }
     cs2 = wave_sum_u32(cs2);
     uint32_t fwp = 0;
-    for (int c = tid; c < k; c += BLOCK) fwp += m1[c];
+    for (int c = tid; c < k; c += BLOCK) {
+      fwp += cls[c].x;
+      m1v[c] = cls[c].x;
+    }
     fwp = wave_sum_u32(fwp);
     if (lane == 0) {
       s_red[wid] = (int32_t)cs2;
@@ -185,196 +203,234 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
     if (conf == 0 && fw < best_legal) {
       best_legal = fw;
       if (wid == 0)
-        for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffffu);
+        for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(vinfo[v].x & 0xffffu);
     }
+    __syncthreads();  // s_red is reused by the next round
 
     for (int it = 0; it < a.T; ++it, ++t) {
       const int par = (t & 1) * NW;
-      if (wid == 0 && t - Lbase >= 64) {
-        Lbase = t;
-        Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, a.key), (uint32_t)a.ten_rand);
-      }
-      const int64_t asp = G_best - G - 1;
-      // ---- scan every one-move (v, c), c != col v
+      if (wid == 0 && (t & 63) == 0)
+        Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, key), (uint32_t)a.ten_rand);
+      const int64_t asp = G_best - G - 1;  // aspiration: G + dg < G_best
+
+      // ---- scan every one-move (v, c), c != col v, one quad of colours at a time
       uint64_t bd = ~0ull;
-      uint32_t bidx = 0xffffffffu, bcnt = 0, s0 = 0, s1 = 0;
+      uint32_t cnt = 0, s0 = 0, s1 = 0;
+      auto eval_quad = [&](int v, int q, auto&& fn) {
+        const uint4 vi = vinfo[v];
+        const uint32_t cv = vi.x & 0xffffu, gcur = vi.x >> 16, wv = vi.y;
+        const bool fr = (int)vi.z <= t;
+        const uint4 ca = cls[cv];
+        const int32_t base_fw = (int32_t)((wv < ca.x || ca.y > 1u) ? ca.x : ca.z) - (int32_t)ca.x;
+        const uint4 m4 = *reinterpret_cast<const uint4*>(m1v + 4 * q);
+        const uint2 g2 = *reinterpret_cast<const uint2*>(gam + v * kp + 4 * q);
+        const uint32_t gq[4] = {g2.x & 0xffffu, g2.x >> 16, g2.y & 0xffffu, g2.y >> 16};
+        const uint32_t mq[4] = {m4.x, m4.y, m4.z, m4.w};
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int c = 4 * q + rr;
+          const int32_t dfw = (int32_t)(max(mq[rr], wv) - mq[rr]) + base_fw;
+          const int32_t dcf = (int32_t)gq[rr] - (int32_t)gcur;
+          const int64_t dg = ((int64_t)dfw << S) + (int64_t)phi32 * dcf;
+          const bool adm = c < k && (uint32_t)c != cv && (fr || dg <= asp);
+          fn(((uint32_t)v << 16) | (uint32_t)c, adm ? (uint64_t)dg + kGBias : ~0ull);
+        }
+      };
+      auto consider = [&](uint32_t idx, uint64_t b) {
+        const bool lt = b < bd, eq = b == bd;
+        s1 = (eq && cnt == 1u) ? idx : s1;
+        cnt = lt ? 1u : cnt + (eq ? 1u : 0u);
+        s0 = lt ? idx : s0;
+        bd = lt ? b : bd;
+      };
       {
-        int i = i0, c = c0;
-        for (int j = tid; j < nk; j += BLOCK) {
-          const int v = i;
-          const uint32_t x = cg[v];
-          const int cv = (int)(x & 0xffffu);
-          if (c != cv) {
-            const uint32_t wv = (uint32_t)w[v];
-            const uint32_t am1 = m1[cv];
-            const uint32_t m_after = (wv < am1 || c1[cv] > 1u) ? am1 : m2[cv];
-            const uint32_t bm1 = m1[c];
-            const int64_t dfw = (int64_t)(max(bm1, wv) - bm1) + ((int64_t)m_after - (int64_t)am1);
-            const int64_t dcf = (int64_t)gam[v * k + c] - (int64_t)(x >> 16);
-            const int64_t dg = (dfw << S) + phi * dcf;
-            if (frozen[v] <= t || dg <= asp) {
-              const uint64_t key = (uint64_t)dg + kGBias;
-              const uint32_t idx = ((uint32_t)v << 16) | (uint32_t)c;
-              if (key < bd) {
-                bd = key;
-                bidx = idx;
-                bcnt = 1;
-                s0 = idx;
-              } else if (key == bd) {
-                bidx = min(bidx, idx);
-                if (bcnt == 1) s1 = idx;
-                ++bcnt;
-              }
-            }
+        int i = i0, q = q0;
+        for (int j = tid; j < totq; j += BLOCK) {
+          eval_quad(i, q, consider);
+          step(i, q);
+        }
+      }
+
+      // ---- wave result: smallest (key, Philox word, v, c); the moves tied at
+      // the wave's best key are staged in LDS and hashed in one pass
+      const uint64_t wbd = wave_min_u64(bd);
+      uint64_t hk = ~0ull;
+      if (wbd != ~0ull) {
+        auto hkey = [&](uint32_t idx) -> uint64_t {
+          return ((uint64_t)philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key) << 32) | idx;
+        };
+        const bool tie = bd == wbd;
+        const bool A = tie && cnt <= 2u, B = tie && cnt == 2u, Rr = tie && cnt > 2u;
+        const uint64_t mA = __ballot(A), mB = __ballot(B);
+        const uint32_t nR = wave_sum_u32(Rr ? cnt : 0u);
+        const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
+        const uint32_t total = nA + nB + nR;
+        auto rescan = [&](auto&& sink) {
+          int i = i0, q = q0;
+          for (int j = tid; j < totq; j += BLOCK) {
+            eval_quad(i, q, [&](uint32_t idx, uint64_t b) {
+              if (b == wbd) sink(idx);
+            });
+            step(i, q);
           }
-          c += dc;
-          i += di;
-          if (c >= k) {
-            c -= k;
-            ++i;
+        };
+        if (total <= (uint32_t)kWStage) {
+          uint32_t* stg = stage + wid * (kWStage + 4);
+          uint32_t* rctr = stg + kWStage;
+          if (lane == 0) *rctr = nA + nB;
+          if (A) stg[__builtin_amdgcn_mbcnt_hi((uint32_t)(mA >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mA, 0u))] = s0;
+          if (B) stg[nA + __builtin_amdgcn_mbcnt_hi((uint32_t)(mB >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mB, 0u))] = s1;
+          if (Rr) {
+            uint32_t p = atomicAdd(rctr, cnt);
+            rescan([&](uint32_t idx) { stg[p++] = idx; });
           }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          for (uint32_t c0 = 0; c0 < total; c0 += kWave)
+            if (c0 + lane < total) hk = umin64(hk, hkey(stg[c0 + lane]));
+        } else {
+          if (A) hk = hkey(s0);
+          if (B) hk = umin64(hk, hkey(s1));
+          if (Rr) rescan([&](uint32_t idx) { hk = umin64(hk, hkey(idx)); });
         }
       }
       {
-        const uint64_t wk = wave_min_u64(bd);
-        const uint64_t wi = wave_min_u64(bd == wk ? (uint64_t)bidx : ~0ull);
-        const uint32_t wc = wave_sum_u32(bd == wk ? bcnt : 0u);
+        const uint64_t whk = wave_min_u64(hk);
+        const uint32_t wcnt = wave_sum_u32(bd == wbd ? cnt : 0u);
+        // the chosen vertex's colour and gamma, read while no wave writes them
+        uint32_t wold = 0, wdcf = 0;
+        if (wbd != ~0ull) {
+          const uint32_t v = (uint32_t)whk >> 16, c = (uint32_t)whk & 0xffffu;
+          const uint32_t x = vinfo[v].x;
+          wold = x & 0xffffu;
+          wdcf = (uint32_t)((int32_t)gam[v * kp + (int)c] - (int32_t)(x >> 16));
+        }
         if (lane == 0) {
-          rkey[par + wid] = wk;
-          ridx[par + wid] = (uint32_t)wi;
-          rcnt[par + wid] = wc;
+          uint32_t* e = red + (par + wid) * 8;
+          *reinterpret_cast<uint4*>(e) = make_uint4((uint32_t)wbd, (uint32_t)(wbd >> 32), wcnt, (uint32_t)whk);
+          *reinterpret_cast<uint4*>(e + 4) = make_uint4((uint32_t)(whk >> 32), wold, wdcf, 0u);
         }
       }
       __syncthreads();
-      uint64_t gk = rkey[par];
+      // cross-wave: smallest (key, hash, v, c), folded in scalar registers
+      auto rfl = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
+      uint64_t gk, gh;
+      uint32_t gcnt, gold, gdcf;
+      {
+        const uint4 e0 = *reinterpret_cast<const uint4*>(red + par * 8);
+        const uint4 e1 = *reinterpret_cast<const uint4*>(red + par * 8 + 4);
+        gk = ((uint64_t)rfl(e0.y) << 32) | rfl(e0.x);
+        gcnt = rfl(e0.z);
+        gh = ((uint64_t)rfl(e1.x) << 32) | rfl(e0.w);
+        gold = rfl(e1.y);
+        gdcf = rfl(e1.z);
+      }
 #pragma unroll
-      for (int q = 1; q < NW; ++q) gk = umin64(gk, rkey[par + q]);
-      uint32_t gcnt = 0, gidx = 0xffffffffu;
-#pragma unroll
-      for (int q = 0; q < NW; ++q)
-        if (rkey[par + q] == gk) {
-          gcnt += rcnt[par + q];
-          gidx = min(gidx, ridx[par + q]);
-        }
+      for (int q = 1; q < NW; ++q) {
+        const uint4 e0 = *reinterpret_cast<const uint4*>(red + (par + q) * 8);
+        const uint4 e1 = *reinterpret_cast<const uint4*>(red + (par + q) * 8 + 4);
+        const uint64_t ek = ((uint64_t)rfl(e0.y) << 32) | rfl(e0.x);
+        const uint64_t eh = ((uint64_t)rfl(e1.x) << 32) | rfl(e0.w);
+        const uint32_t ec = rfl(e0.z), eo = rfl(e1.y), ed = rfl(e1.z);
+        gcnt = ek < gk ? ec : (ek == gk ? gcnt + ec : gcnt);
+        const bool take = ek < gk || (ek == gk && eh < gh);
+        gk = take ? ek : gk;
+        gh = take ? eh : gh;
+        gold = take ? eo : gold;
+        gdcf = take ? ed : gdcf;
+      }
       if (gk == ~0ull) {  // nothing admissible
-        if (wid == 0) {
+        if (wid == 0 && lane == 0) {
           ++st_noops;
           fp = fnv_step(fp, 0xffffu, 0xffffu, (int32_t)(G >> S));
         }
         continue;
       }
-      uint32_t win = gidx;
-      if (gcnt > 1) {
-        uint64_t hk = ~0ull;
-        if (bd == gk) {
-          auto hkey = [&](uint32_t idx) -> uint64_t {
-            return ((uint64_t)philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, a.key) << 32) | idx;
-          };
-          if (bcnt <= 2) {
-            hk = hkey(s0);
-            if (bcnt == 2) hk = umin64(hk, hkey(s1));
-          } else {
-            int i = i0, c = c0;
-            for (int j = tid; j < nk; j += BLOCK) {
-              const int v = i;
-              const uint32_t x = cg[v];
-              const int cv = (int)(x & 0xffffu);
-              if (c != cv) {
-                const uint32_t wv = (uint32_t)w[v];
-                const uint32_t am1 = m1[cv];
-                const uint32_t m_after = (wv < am1 || c1[cv] > 1u) ? am1 : m2[cv];
-                const uint32_t bm1 = m1[c];
-                const int64_t dfw = (int64_t)(max(bm1, wv) - bm1) + ((int64_t)m_after - (int64_t)am1);
-                const int64_t dcf = (int64_t)gam[v * k + c] - (int64_t)(x >> 16);
-                const int64_t dg = (dfw << S) + phi * dcf;
-                if ((uint64_t)dg + kGBias == gk && (frozen[v] <= t || dg <= asp))
-                  hk = umin64(hk, hkey(((uint32_t)v << 16) | (uint32_t)c));
-              }
-              c += dc;
-              i += di;
-              if (c >= k) {
-                c -= k;
-                ++i;
-              }
-            }
-          }
-        }
-        hk = wave_min_u64(hk);
-        if (lane == 0) rhash[par + wid] = hk;
-        __syncthreads();
-        uint64_t gh = rhash[par];
-#pragma unroll
-        for (int q = 1; q < NW; ++q) gh = umin64(gh, rhash[par + q]);
-        win = (uint32_t)gh;
-      }
-      // ---- apply (wave 0)
-      const int vs = (int)(win >> 16), cs = (int)(win & 0xffffu);
+      const uint32_t win = (uint32_t)gh;
+      const int vs = (int)(win >> 16), cs = (int)(win & 0xffffu), old = (int)gold;
       const int64_t dg = (int64_t)(gk - kGBias);
-      if (wid == 0) {
-        const uint32_t xs = cg[vs];
-        const int old = (int)(xs & 0xffffu);
-        const int64_t dcs = (int64_t)gam[vs * k + cs] - (int64_t)(xs >> 16);
-        const int rs = a.row_ptr[vs], re = a.row_ptr[vs + 1];
-        for (int e = rs + lane; e < re; e += kWave) {
-          const int u = a.col_idx[e];
-          const int io = u * k + old, ic = u * k + cs;
+      const int rs = a.row_ptr[vs], re = a.row_ptr[vs + 1];
+
+      // ---- apply: every thread takes a share of the neighbours of v*
+      {
+        auto update = [&](int u) {
+          const int io = u * kp + old, ic = u * kp + cs;
           atomicAdd(reinterpret_cast<uint32_t*>(gam) + (io >> 1), (io & 1) ? 0xffff0000u : 0xffffffffu);
           atomicAdd(reinterpret_cast<uint32_t*>(gam) + (ic >> 1), (ic & 1) ? 0x10000u : 1u);
-          const uint32_t xu = cg[u];
-          const int cu = (int)(xu & 0xffffu);
-          if (cu == old) cg[u] = xu - 0x10000u;
-          else if (cu == cs) cg[u] = xu + 0x10000u;
+          const uint32_t xu = vinfo[u].x;
+          const uint32_t cu = xu & 0xffffu;
+          vinfo[u].x = xu - (cu == (uint32_t)old ? 0x10000u : 0u) + (cu == (uint32_t)cs ? 0x10000u : 0u);
+        };
+        constexpr int kPre = BLOCK >= 256 ? 2 : 4;
+        int nb[kPre];
+#pragma unroll
+        for (int q = 0; q < kPre; ++q) {
+          const int e = rs + tid + q * BLOCK;
+          nb[q] = e < re ? col_idx[e] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < kPre; ++q)
+          if (nb[q] >= 0) update(nb[q]);
+        for (int e = rs + kPre * BLOCK + tid; e < re; e += BLOCK) update(col_idx[e]);
+      }
+      if (wid == 0) {
+        const uint32_t Lt = readlane(Lreg, t & 63);
+        const uint32_t wv = vinfo[vs].y;
+        if (lane == 0) {
+          vinfo[vs].x = (uint32_t)cs | ((uint32_t)gam[vs * kp + cs] << 16);
+          vinfo[vs].z = (uint32_t)(t + (int)Lt + a.frz);
+          // class c* gains v*
+          const uint4 cb = cls[cs];
+          const uint32_t nm1 = max(cb.x, wv);
+          const uint32_t nc1 = wv > cb.x ? 1u : (wv == cb.x ? cb.y + 1u : cb.y);
+          const uint32_t nm2 = wv > cb.x ? cb.x : (wv == cb.x ? cb.z : max(cb.z, wv));
+          cls[cs] = make_uint4(nm1, nc1, nm2, 0u);
+          m1v[cs] = nm1;
+        }
+        // class old loses v*: its triple changes without a rescan unless v*
+        // carried its largest weight alone or its second largest
+        const uint4 ca = cls[old];
+        if (wv == ca.x && ca.y > 1u) {
+          if (lane == 0) cls[old].y = ca.y - 1u;
+        } else if (wv == ca.x || wv == ca.z) {
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          Cls acc{0, 0, 0};
+          for (int v = lane; v < n; v += kWave) {
+            const uint4 vi = vinfo[v];
+            if ((vi.x & 0xffffu) == (uint32_t)old) acc = cls_join(acc, Cls{vi.y, 1u, 0u});
+          }
+          acc = wave_cls(acc);
+          if (lane == 0) {
+            cls[old] = make_uint4(acc.m1, acc.c1, acc.m2, 0u);
+            m1v[old] = acc.m1;
+          }
         }
         if (lane == 0) {
-          cg[vs] = (uint32_t)cs | ((uint32_t)gam[vs * k + cs] << 16);
-          frozen[vs] = t + (int)readlane(Lreg, t - Lbase) + a.frz;
+          st_deg += (uint64_t)(re - rs);
+          st_ties += gcnt > 1u;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // class statistics of the two classes touched
-        Cls ca{0, 0, 0}, cb{0, 0, 0};
-        for (int v = lane; v < n; v += kWave) {
-          const int c = (int)(cg[v] & 0xffffu);
-          const Cls one{(uint32_t)w[v], 1u, 0u};
-          if (c == old) ca = cls_join(ca, one);
-          else if (c == cs) cb = cls_join(cb, one);
-        }
-        ca = wave_cls(ca);
-        cb = wave_cls(cb);
-        if (lane == 0) {
-          m1[old] = ca.m1;
-          c1[old] = ca.c1;
-          m2[old] = ca.m2;
-          m1[cs] = cb.m1;
-          c1[cs] = cb.c1;
-          m2[cs] = cb.m2;
-        }
-        if (lane == 0) s_dcs = (int32_t)dcs;
-        ++st_moves;
-        st_deg += (uint64_t)(re - rs);
-        st_ties += gcnt > 1;
       }
       __syncthreads();
-      conf += s_dcs;
+      conf += (int32_t)gdcf;
       G += dg;
       fw = (G - phi * conf) >> S;
-      if (wid == 0) fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, (int32_t)(G >> S));
-      const bool new_best_g = G < G_best;
-      const bool new_legal = conf == 0 && fw < best_legal;
-      if (new_best_g) {
+      if (wid == 0 && lane == 0) fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, (int32_t)(G >> S));
+      if (G < G_best) {
         G_best = G;
         conf_best = conf;
-        for (int v = tid; v < n; v += BLOCK) bestg[v] = (int16_t)(cg[v] & 0xffffu);
+        for (int v = tid; v < n; v += BLOCK) bestg[v] = (int16_t)(vinfo[v].x & 0xffffu);
       }
-      if (new_legal) {
+      if (conf == 0 && fw < best_legal) {
         best_legal = fw;
         if (wid == 0)
-          for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffffu);
+          for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(vinfo[v].x & 0xffffu);
       }
     }
     // next round starts from bestg (already in LDS); adapt phi
     const bool legal = conf_best == 0;
-    st_legal_rounds += legal;
+    if (wid == 0 && lane == 0) st_legal_rounds += legal;
     if (r < a.R - 1) phi = legal ? (phi >> 1) : min(phi << 1, phi_max);
     __syncthreads();
   }
@@ -385,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
       a.best_legal[li] = best_legal == INT64_MAX ? 0x7fffffff : (int32_t)best_legal;
       if (a.stats) {
         int64_t* s = a.stats + (size_t)li * DLM_NSTATS;
-        s[0] = (int64_t)st_moves;
+        s[0] = (int64_t)(t - (int)st_noops);
         s[1] = (int64_t)st_noops;
         s[2] = (int64_t)st_deg;
         s[3] = (int64_t)st_ties;
@@ -426,6 +482,9 @@ extern "C" int dlm_wvcp_batch(const dlm_graph* g, const dlm_wvcp_params* p, int3
   if (p->frz_den <= 0 || p->frz_num < 0 || p->frz_num > 1024)
     return set_error(DLM_E_INVAL, "dlm_wvcp_batch: freeze slope %d/%d invalid", p->frz_num, p->frz_den);
   if (p->shift < 0 || p->shift > 16) return set_error(DLM_E_INVAL, "dlm_wvcp_batch: shift=%d outside [0, 16]", p->shift);
+  if (((int64_t)2 * g->max_w << p->shift) > (1ll << 30))
+    return set_error(DLM_E_UNSUPPORTED, "dlm_wvcp_batch: 2 * max weight (%d) << shift (%d) exceeds 2^30", g->max_w,
+                     p->shift);
   if (p->ind_base < 0 || (int64_t)p->ind_base + pop > 0x7fffffffll)
     return set_error(DLM_E_INVAL, "dlm_wvcp_batch: ind_base + pop exceeds 2^31");
   if (p->reserved != 0) return set_error(DLM_E_INVAL, "dlm_wvcp_batch: reserved must be 0");
