@@ -41,7 +41,7 @@ struct WvcpArgs {
   int64_t* stats;
   uint64_t* hash;
   Key key;
-  int32_t n, k, T, R, ten_rand, frz, shift, ind_base, max_w;
+  int32_t n, k, T, R, ten_rand, frz, shift, ind_base, max_w, max_deg;
 };
 
 // gamma rows are padded to kp = k rounded up to 4 colours (one 8-byte read
@@ -155,6 +155,8 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
   for (int r = 0; r < a.R; ++r) {
     if (r == a.R - 1) phi = (int64_t)(2 * a.max_w) << S;
     const int32_t phi32 = (int32_t)phi;  // phi <= 2^30
+    // |dg| <= (max_w << S) + phi * max_deg: 32-bit keys when that stays below 2^31 - 1
+    const bool k32_round = ((int64_t)a.max_w << S) + phi * (int64_t)a.max_deg < (int64_t)INT32_MAX - 1;
     // ---- fresh round state from the best-g colouring of the previous round
     for (int i = tid; i < n * kp / 2; i += BLOCK) reinterpret_cast<uint32_t*>(gam)[i] = 0u;
     for (int v = tid; v < n; v += BLOCK)
@@ -213,8 +215,14 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
         Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, key), (uint32_t)a.ten_rand);
       const int64_t asp = G_best - G - 1;  // aspiration: G + dg < G_best
 
-      // ---- scan every one-move (v, c), c != col v, one quad of colours at a time
-      uint64_t bd = ~0ull;
+      // ---- scan every one-move (v, c), c != col v, one quad of colours at a time.
+      // Keys are dg + bias in 32 bits when the round's bound allows it, else 64.
+      auto pick = [&](auto key_zero) {
+      using KT = decltype(key_zero);
+      constexpr bool k32 = sizeof(KT) == 4;
+      constexpr KT kNoKey = (KT)~(KT)0;
+      const int32_t asp32 = (int32_t)max<int64_t>(min<int64_t>(asp, INT32_MAX), INT32_MIN);
+      KT bd = kNoKey;
       uint32_t cnt = 0, s0 = 0, s1 = 0;
       auto eval_quad = [&](int v, int q, auto&& fn) {
         const uint4 vi = vinfo[v];
@@ -231,12 +239,18 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
           const int c = 4 * q + rr;
           const int32_t dfw = (int32_t)(max(mq[rr], wv) - mq[rr]) + base_fw;
           const int32_t dcf = (int32_t)gq[rr] - (int32_t)gcur;
-          const int64_t dg = ((int64_t)dfw << S) + (int64_t)phi32 * dcf;
-          const bool adm = c < k && (uint32_t)c != cv && (fr || dg <= asp);
-          fn(((uint32_t)v << 16) | (uint32_t)c, adm ? (uint64_t)dg + kGBias : ~0ull);
+          if constexpr (k32) {
+            const int32_t dg = dfw * (int32_t)(1 << S) + phi32 * dcf;  // |dg| < 2^31 - 1 this round
+            const bool adm = c < k && (uint32_t)c != cv && (fr || dg <= asp32);
+            fn(((uint32_t)v << 16) | (uint32_t)c, adm ? (KT)((uint32_t)dg + 0x80000000u) : kNoKey);
+          } else {
+            const int64_t dg = (int64_t)dfw * ((int64_t)1 << S) + (int64_t)phi32 * dcf;
+            const bool adm = c < k && (uint32_t)c != cv && (fr || dg <= asp);
+            fn(((uint32_t)v << 16) | (uint32_t)c, adm ? (KT)((uint64_t)dg + kGBias) : kNoKey);
+          }
         }
       };
-      auto consider = [&](uint32_t idx, uint64_t b) {
+      auto consider = [&](uint32_t idx, KT b) {
         const bool lt = b < bd, eq = b == bd;
         s1 = (eq && cnt == 1u) ? idx : s1;
         cnt = lt ? 1u : cnt + (eq ? 1u : 0u);
@@ -253,9 +267,11 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
 
       // ---- wave result: smallest (key, Philox word, v, c); the moves tied at
       // the wave's best key are staged in LDS and hashed in one pass
-      const uint64_t wbd = wave_min_u64(bd);
+      KT wbd;
+      if constexpr (k32) wbd = wave_min_u32(bd);
+      else wbd = wave_min_u64(bd);
       uint64_t hk = ~0ull;
-      if (wbd != ~0ull) {
+      if (wbd != kNoKey) {
         auto hkey = [&](uint32_t idx) -> uint64_t {
           return ((uint64_t)philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key) << 32) | idx;
         };
@@ -268,7 +284,7 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
         auto rescan = [&](auto&& sink) {
           int i = i0, q = q0;
           for (int j = tid; j < totq; j += BLOCK) {
-            eval_quad(i, q, [&](uint32_t idx, uint64_t b) {
+            eval_quad(i, q, [&](uint32_t idx, KT b) {
               if (b == wbd) sink(idx);
             });
             step(i, q);
@@ -300,18 +316,28 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
         const uint32_t wcnt = wave_sum_u32(bd == wbd ? cnt : 0u);
         // the chosen vertex's colour and gamma, read while no wave writes them
         uint32_t wold = 0, wdcf = 0;
-        if (wbd != ~0ull) {
+        if (wbd != kNoKey) {
           const uint32_t v = (uint32_t)whk >> 16, c = (uint32_t)whk & 0xffffu;
           const uint32_t x = vinfo[v].x;
           wold = x & 0xffffu;
           wdcf = (uint32_t)((int32_t)gam[v * kp + (int)c] - (int32_t)(x >> 16));
         }
+        // the slot holds the 64-bit key (dg + 2^62) whichever width the scan used
+        uint64_t wk64 = ~0ull;
+        if constexpr (k32) {
+          if (wbd != kNoKey) wk64 = (uint64_t)(int64_t)(int32_t)((uint32_t)wbd - 0x80000000u) + kGBias;
+        } else {
+          wk64 = wbd;
+        }
         if (lane == 0) {
           uint32_t* e = red + (par + wid) * 8;
-          *reinterpret_cast<uint4*>(e) = make_uint4((uint32_t)wbd, (uint32_t)(wbd >> 32), wcnt, (uint32_t)whk);
+          *reinterpret_cast<uint4*>(e) = make_uint4((uint32_t)wk64, (uint32_t)(wk64 >> 32), wcnt, (uint32_t)whk);
           *reinterpret_cast<uint4*>(e + 4) = make_uint4((uint32_t)(whk >> 32), wold, wdcf, 0u);
         }
       }
+      };
+      if (k32_round) pick(0u);
+      else pick(0ull);
       __syncthreads();
       // cross-wave: smallest (key, hash, v, c), folded in scalar registers
       auto rfl = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
@@ -498,7 +524,7 @@ extern "C" int dlm_wvcp_batch(const dlm_graph* g, const dlm_wvcp_params* p, int3
     return set_error(DLM_E_UNSUPPORTED, "dlm_wvcp_batch: %zu bytes of LDS needed", lds);
   WvcpArgs a{g->row_ptr, g->col_idx, g->erow, g->weights, colors, best_legal, stats, hash,
              make_key(p->seed), g->n, p->k, p->iters_per_round, p->rounds, p->ten_rand,
-             (int32_t)((int64_t)p->frz_num * g->n / p->frz_den), p->shift, p->ind_base, g->max_w};
+             (int32_t)((int64_t)p->frz_num * g->n / p->frz_den), p->shift, p->ind_base, g->max_w, g->max_deg};
   hipStream_t s = (hipStream_t)stream;
   switch (block) {
     case 64: return launch_wvcp<64>(a, pop, lds, s);

@@ -86,3 +86,33 @@ def test_wvcp300_sampled(dlm, dev):
     legal = bl != 2**31 - 1
     assert (conf.cpu().numpy()[legal] == 0).all()
     assert (ws.cpu().numpy()[legal] == bl[legal]).all()
+
+
+def test_wvcp_wide_keys(dlm, dev):
+    """Heavy weights with 16 fractional bits of phi: phi * max degree passes
+    2^31, so the search keys its moves in 64 bits; results still equal the
+    oracle's."""
+    n, shift = 60, 16
+    g = gnp(n, 0.5, seed=8).with_weights(uniform_weights(n, 1000, 8000, seed=9))
+    max_deg = int(np.diff(g.row_ptr).max())
+    pop, T, R = 4, 300, 6
+    starts, ks = [], []
+    for i in range(pop):
+        c, u = oracle.greedy_init(g, seed=1, ind=i)
+        starts.append(c)
+        ks.append(u)
+    k = max(ks) + 1
+    max_w = int(g.weights.max())
+    phi0 = (k * max_w << shift) // (2 * n)
+    assert (max_w << shift) + phi0 * max_deg > 2**31  # the 64-bit path from the first round
+    assert (2 * max_w) << shift <= 2**30             # within the supported weight range
+    starts = np.stack(starts)
+    ref = oracle.wvcp_batch(g, starts, np.arange(pop), k, T, R, seed=3, shift=shift)
+    G = dlm.Graph.from_csr(g)
+    say(f"wvcp wide keys n={n} k={k} shift={shift}")
+    r = dlm.wvcp_batch(G, torch.from_numpy(starts).cuda(), k, T, R, seed=3, shift=shift, block=128)
+    torch.cuda.synchronize()
+    assert (r["best_legal"].cpu().numpy() == ref["best_legal"]).all()
+    assert (r["stats"].cpu().numpy()[:, :6] == ref["stats"][:, :6]).all()
+    assert (r["hash"].cpu().numpy().view(np.uint64) == ref["hash"]).all()
+    assert (r["colors"].cpu().numpy() == ref["colors"]).all()
