@@ -125,7 +125,8 @@ typedef struct dlm_tabu_params {
   int32_t ten_rand;   /* L uniform in [0, ten_rand), 1..1024 */
   int32_t ind_base;   /* global index of row 0 of the population */
   uint64_t seed;      /* Philox key */
-  int32_t block;      /* threads per workgroup: 0 = auto, else 64, 128, 256, 512 or 1024 */
+  int32_t block;      /* threads per workgroup: 0 = auto (256; 512 when AUTO storage fits only one
+                         individual per CU), else 64, 128, 256, 512 or 1024 */
   int32_t table;      /* DLM_TABLE_* storage of the n x k table */
   int32_t trace_cap;  /* records per individual in trace_dev (0 = none) */
   int32_t reserved;   /* must be 0 */

@@ -143,19 +143,23 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
   if (p->reserved != 0) return set_error(DLM_E_INVAL, "dlm_tabu_batch: reserved must be 0");
   if (pop == 0) return DLM_OK;
   if (!colors || !f_best || !iters) return set_error(DLM_E_INVAL, "dlm_tabu_batch: null output buffer");
-  const int block = p->block ? p->block : 256;
-  const int nw = block / kWave;
+  int block = p->block ? p->block : 256;
   const int n = g->n, k = p->k;
   const int64_t lds_max = device_lds_limit();
   int table = p->table;
   if (table == DLM_TABLE_AUTO) {
     // the LDS tier that keeps more individuals resident per CU; byte gamma on a tie loses
-    const uint64_t l16 = tabu_layout(n, k, nw, TabLds16::kLdsBytes).bytes;
-    const uint64_t l8 = tabu_layout(n, k, nw, TabSplit8::kLdsBytes).bytes;
+    const int nw0 = block / kWave;
+    const uint64_t l16 = tabu_layout(n, k, nw0, TabLds16::kLdsBytes).bytes;
+    const uint64_t l8 = tabu_layout(n, k, nw0, TabSplit8::kLdsBytes).bytes;
     const int o16 = l16 <= (uint64_t)lds_max ? resident<TabLds16>(block, l16) : 0;
     const int o8 = l8 <= (uint64_t)lds_max ? resident<TabSplit8>(block, l8) : 0;
     table = o8 > o16 ? DLM_TABLE_SPLIT8 : (o16 > 0 ? DLM_TABLE_LDS16 : DLM_TABLE_GLOBAL16);
+    // automatic block: when a single LDS-resident individual fills a CU, 512
+    // threads hide more of the per-move latency than 256
+    if (p->block == 0 && std::max(o16, o8) == 1 && block == 256) block = 512;
   }
+  const int nw = block / kWave;
   int eb = 0, gb = 0;
   switch (table) {
     case DLM_TABLE_LDS16: eb = TabLds16::kLdsBytes; break;
