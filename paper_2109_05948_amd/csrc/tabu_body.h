@@ -12,7 +12,7 @@ constexpr int kBias = 32768;             // delta + kBias >= 0 for |delta| < 2^1
 constexpr int kRebaseEvery = 16384;      // 16-bit expiries: the origin moves every 2^14 iterations
 constexpr uint32_t kPadGamma = 0x7fffu;  // gamma stored in the padding colours k .. kp-1
 constexpr uint32_t kNone = 0xffffffffu;  // no admissible candidate
-constexpr int kStage = 128;              // tied moves a wave hashes in one staged pass
+constexpr int kStage = 64;               // tied moves a wave hashes in one staged pass
 
 // Table encoding, common to every storage policy:
 //  * the entry (v, col v) of a vertex's current colour holds the expiry
@@ -264,8 +264,9 @@ struct TabuArgs {
 };
 
 struct TabuLayout {
-  uint64_t tab, cg, list, pos, rp, red, stage, csize, sc, bytes;
-  int32_t cap;  // conflict-list capacity (entries)
+  uint64_t tab, cg, list, pos, red, stage, csize, sc, bytes;
+  int32_t cap;      // conflict-list capacity (entries)
+  int32_t len_max;  // longest list a move may start from (rebuilt beyond it)
 };
 
 // Table rows are padded to a multiple of 4 colours so that a quad of
@@ -280,14 +281,16 @@ __host__ __device__ inline TabuLayout tabu_layout(int n, int k, int nw, int entr
   L.tab = o;
   o += ((tab_entries(n, k) * entry_bytes) + 15u) & ~15ull;
   L.cg = o;
-  o += align16(4u * n);
-  L.cap = 2 * n + 32;
+  o += align16(4u * (n + 1));  // cg[n] = 0 belongs to the all-padding row
+  // a move appends at most the members of one colour class: at most 255 of
+  // them with byte gamma (the class bound), at most n otherwise
+  const int max_insert = entry_bytes == 1 ? (n < 255 ? n : 255) : n;
+  L.cap = n + 32 + max_insert < 65535 ? n + 32 + max_insert : 65535;  // 16-bit positions
+  L.len_max = L.cap - max_insert;
   L.list = o;
-  o += align16(4u * L.cap);
+  o += align16(2u * L.cap);
   L.pos = o;
-  o += align16(4u * n);
-  L.rp = o;
-  o += align16(4u * (n + 1));
+  o += align16(2u * n);
   L.red = o;
   o += 2u * 16u * nw;
   L.stage = o;
@@ -300,12 +303,12 @@ __host__ __device__ inline TabuLayout tabu_layout(int n, int k, int nw, int entr
   return L;
 }
 
-constexpr uint32_t kNoPos = 0xffffffffu;
+constexpr uint16_t kNoPos = 0xffffu;
 
 // Wave 0 rebuilds the conflict list from cg (cg[v] = col v | gamma[v][col v] << 16):
-// the conflicting vertices in vertex order as (gamma[v][col v] << 16) | v,
-// pos[v] = index of v in the list or kNoPos.  Returns the list length.
-__device__ __forceinline__ int build_conflict_list(const uint32_t* cg, uint32_t* list, uint32_t* pos, int n,
+// the conflicting vertices in vertex order, pos[v] = index of v in the list
+// or kNoPos.  Returns the list length.
+__device__ __forceinline__ int build_conflict_list(const uint32_t* cg, uint16_t* list, uint16_t* pos, int n,
                                                    int lane) {
   int base = 0;
   for (int v0 = 0; v0 < n; v0 += 4 * kWave) {
@@ -321,8 +324,8 @@ __device__ __forceinline__ int build_conflict_list(const uint32_t* cg, uint32_t*
       const bool cf = x[r] >= 0x10000u;
       const uint64_t m = __ballot(cf);
       const int p = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      if (cf) list[p] = (x[r] & 0xffff0000u) | (uint32_t)v;
-      if (v < n) pos[v] = cf ? (uint32_t)p : kNoPos;
+      if (cf) list[p] = (uint16_t)v;
+      if (v < n) pos[v] = cf ? (uint16_t)p : kNoPos;
       base += __popcll(m);
     }
   }
@@ -358,11 +361,11 @@ __device__ __forceinline__ gptr<T> own_sgpr(T* p) {
 // One individual (row li of a.colors) searched by the calling workgroup.
 // gtab: the device-memory part of this workgroup's table (global and split tiers).
 //
-// The conflict list holds one live entry (gamma[v][col v] << 16 | v) per
-// conflicting vertex and tombstones (0 << 16 | n, the all-padding row) for
-// vertices that stopped conflicting; the move updates it in place and appends
-// new conflicting vertices, and it is rebuilt when tombstones pass a quarter
-// of it.  The chosen move is a minimum over a set, so list order is free.
+// The conflict list holds one live entry (the vertex) per conflicting vertex
+// and tombstones (n, the all-padding row, whose cg word is 0) for vertices
+// that stopped conflicting; a move tombstones and appends in place, and the
+// list is rebuilt when tombstones pass a quarter of it.  The chosen move is a
+// minimum over a set, so list order is free.
 template <int BLOCK, class Tab>
 __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsigned char* gtab,
                                                 unsigned char* smem) {
@@ -380,15 +383,17 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   const TabuLayout L = tabu_layout(n, k, NW, Tab::kLdsBytes);
   Tab tab = Tab::make(smem + L.tab, gtab);
   uint32_t* cg = reinterpret_cast<uint32_t*>(smem + L.cg);
-  uint32_t* list = reinterpret_cast<uint32_t*>(smem + L.list);
-  uint32_t* pos = reinterpret_cast<uint32_t*>(smem + L.pos);
+  uint16_t* list = reinterpret_cast<uint16_t*>(smem + L.list);
+  uint16_t* pos = reinterpret_cast<uint16_t*>(smem + L.pos);
   uint4* red = reinterpret_cast<uint4*>(smem + L.red);
   uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);  // per wave: kStage tied moves + a counter
   uint32_t* csize = reinterpret_cast<uint32_t*>(smem + L.csize);  // class sizes (byte gamma only)
   uint32_t* sc = reinterpret_cast<uint32_t*>(smem + L.sc);  // [0] list length, [1] tombstones
-  int32_t* rp = reinterpret_cast<int32_t*>(smem + L.rp);    // CSR row offsets, cached
   int16_t* gcol = a.colors + (size_t)li * n;
-  const uint32_t kTomb = (uint32_t)n;
+  const uint16_t kTomb = (uint16_t)n;
+  // CSR row offsets through the scalar cache (read-only for the whole launch)
+  const __attribute__((address_space(4))) int32_t* row_c =
+      (const __attribute__((address_space(4))) int32_t*)a.row_ptr;
 
   auto rebuild = [&]() {
     if (wid == 0) {
@@ -416,7 +421,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     return;
   }
   for (int i = tid; i < nk; i += BLOCK) tab.init(i, i >= n * kp || i - (i / kp) * kp >= k);
-  for (int v = tid; v <= n; v += BLOCK) rp[v] = a.row_ptr[v];
+  if (tid == 0) cg[n] = 0u;
   if (Tab::kBounded)
     for (int c = tid; c < kp; c += BLOCK) csize[c] = 0u;
   __syncthreads();
@@ -473,7 +478,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
 
   while (t < T && f > 0) {
     int len = (int)sc[0], dead = (int)sc[1];
-    if (4 * dead > len || len > n + 32) {  // compact (every thread read sc before this barrier)
+    if (4 * dead > len || len > L.len_max) {  // compact (every thread read sc before this barrier)
       __syncthreads();
       rebuild();
       len = (int)sc[0];
@@ -506,12 +511,11 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       bd = lt ? b : bd;
     };
     auto do_quad = [&](int i, int q, auto&& fn) {
-      const uint32_t e = list[i];
-      const uint32_t v = e & 0xffffu;
+      const uint32_t v = list[i];
       uint32_t g4[4];
       bool f4[4];
       Tab::eval4(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), thr, g4, f4);
-      const uint32_t boff = (uint32_t)kBias - (e >> 16);
+      const uint32_t boff = (uint32_t)kBias - (cg[v] >> 16);
       const uint32_t idx = (v << 16) | (uint32_t)(4 * q);
 #pragma unroll
       for (int r = 0; r < 4; ++r) fn(idx + r, g4[r], f4[r], boff);
@@ -525,10 +529,10 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         step(i, q);
         const int ib = i, qb = q;
         step(i, q);
-        const uint32_t ea = list[ia], eb = list[ib];
-        const uint32_t va = ea & 0xffffu, vb = eb & 0xffffu;
+        const uint32_t va = list[ia], vb = list[ib];
         const typename Tab::Raw ra = tab.load4((int)__umul24(va, (uint32_t)kp) + 4 * qa);
         const typename Tab::Raw rb = tab.load4((int)__umul24(vb, (uint32_t)kp) + 4 * qb);
+        const uint32_t ea = cg[va], eb = cg[vb];
         uint32_t ga[4], gb[4];
         bool fa[4], fb[4];
         Tab::eval4(ra, thr, ga, fa);
@@ -659,7 +663,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     const int vs = (int)(win >> 16), cs = (int)(win & 0xffffu), old = (int)((bx >> 16) & 0x7fffu);
     const int fnew = f + ((int)gbd - kBias);
     const bool snap = best_cur && fnew >= f_best;  // leaving the best state: keep a copy
-    const int rs = rp[vs], re = rp[vs + 1];
+    const int rs = row_c[vs], re = row_c[vs + 1];
     if (wid == 0 && snap)
       for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffffu);
     {
@@ -677,7 +681,6 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
           lo = cu == (uint32_t)old;
           hi = cu == (uint32_t)cs;
           cg[u] = xu - (lo ? 0x10000u : 0u) + (hi ? 0x10000u : 0u);
-          if ((lo && gu > 1u) || (hi && gu > 0u)) list[pos[u]] = ((hi ? gu + 1u : gu - 1u) << 16) | (uint32_t)u;
           if (lo && gu == 1u) {
             list[pos[u]] = kTomb;
             pos[u] = kNoPos;
@@ -686,8 +689,8 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         const bool ins = hi && gu == 0u;
         const uint32_t p = wave_append(&sc[0], ins, lane);
         if (ins) {
-          list[p] = (1u << 16) | (uint32_t)u;
-          pos[u] = p;
+          list[p] = (uint16_t)u;
+          pos[u] = (uint16_t)p;
         }
         (void)wave_append(&sc[1], lo && gu == 1u, lane);
       };
@@ -728,8 +731,6 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
           list[pos[vs]] = kTomb;
           pos[vs] = kNoPos;
           atomicAdd(&sc[1], 1u);
-        } else {
-          list[pos[vs]] = (gnew << 16) | (uint32_t)vs;
         }
         if (trace && t < trace_cap) {
           gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
