@@ -388,7 +388,8 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   uint4* red = reinterpret_cast<uint4*>(smem + L.red);
   uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);  // per wave: kStage tied moves + a counter
   uint32_t* csize = reinterpret_cast<uint32_t*>(smem + L.csize);  // class sizes (byte gamma only)
-  uint32_t* sc = reinterpret_cast<uint32_t*>(smem + L.sc);  // [0] list length, [1] tombstones
+  uint32_t* sc = reinterpret_cast<uint32_t*>(smem + L.sc);  // [0] list length, [1] tombstones, [2..3] best delta
+                                                            // published so far (by iteration parity)
   int16_t* gcol = a.colors + (size_t)li * n;
   const uint16_t kTomb = (uint16_t)n;
   // CSR row offsets through the scalar cache (read-only for the whole launch)
@@ -421,7 +422,11 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     return;
   }
   for (int i = tid; i < nk; i += BLOCK) tab.init(i, i >= n * kp || i - (i / kp) * kp >= k);
-  if (tid == 0) cg[n] = 0u;
+  if (tid == 0) {
+    cg[n] = 0u;
+    sc[2] = kNone;
+    sc[3] = kNone;
+  }
   if (Tab::kBounded)
     for (int c = tid; c < kp; c += BLOCK) csize[c] = 0u;
   __syncthreads();
@@ -553,8 +558,17 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     // gathered in LDS (two per lane from registers, more by a rescan of the
     // lane's quads) so that one Philox evaluation per lane covers up to 64.
     const uint32_t wbd = wave_min_u32(bd);
+    // publish the wave's best delta; a wave beaten by an earlier one cannot
+    // hold the chosen move and skips the hashing
+    bool live = wbd != kNone;
+    if (live) {
+      uint32_t prev = 0u;
+      if (lane == 0) prev = atomicMin(&sc[2 + (t & 1)], wbd);
+      live = readlane(prev, 0) >= wbd;
+    }
     uint64_t hk = ~0ull;
-    if (wbd != kNone) {
+    uint32_t wcnt = 0u;
+    if (live) {
       auto hkey = [&](uint32_t idx) -> uint64_t {
         const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key);
         return ((uint64_t)h << 32) | idx;
@@ -569,6 +583,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       const uint32_t nR = wave_sum_u32(R ? cnt : 0u);
       const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
       const uint32_t total = nA + nB + nR;
+      wcnt = total;  // every move of this wave at its best delta
       if (total <= (uint32_t)kStage) {
         uint32_t* stg = stage + wid * (kStage + 4);
         uint32_t* rctr = stg + kStage;
@@ -606,17 +621,18 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
       }
     }
     {
-      const uint64_t whk = wave_min_u64(hk);
-      const uint32_t wcnt = wave_sum_u32(bd == wbd ? cnt : 0u);
+      const uint64_t whk = live ? wave_min_u64(hk) : ~0ull;
       // colour of this wave's chosen vertex, read while no wave writes cg,
       // and (byte gamma) whether the move would grow a class past 255
-      const uint32_t wold = wbd != kNone ? (cg[(uint32_t)whk >> 16] & 0xffffu) : 0u;
-      const uint32_t ovf = Tab::kBounded && wbd != kNone && csize[(uint32_t)whk & 0xffffu] >= 255u ? 1u : 0u;
+      const uint32_t wold = live ? (cg[(uint32_t)whk >> 16] & 0xffffu) : 0u;
+      const uint32_t ovf = Tab::kBounded && live && csize[(uint32_t)whk & 0xffffu] >= 255u ? 1u : 0u;
       if (lane == 0)
         red[par + wid] = make_uint4((wbd & 0xffffu) | (wold << 16) | (ovf << 31), wcnt, (uint32_t)whk,
                                     (uint32_t)(whk >> 32));
     }
     __syncthreads();
+    // every wave has published: the slot is free again for iteration t + 2
+    if (tid == 0) sc[2 + (t & 1)] = kNone;
     // cross-wave: smallest (delta, hash, v, c); tie count over the waves at
     // that delta.  The slots are uniform: fold them in scalar registers.
     auto rfl = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
