@@ -1,27 +1,32 @@
 // Population TabuCol for k-COL (Section 2.7 of the paper: TabuCol with the
 // gamma table of its efficient implementation), one workgroup per individual.
 //
-// Per individual, in LDS (or device memory for tables too large for LDS):
-//   tab[v*k + c]  gamma[v][c] (neighbours of v coloured c) and the tabu
-//                 expiry of (v, c); LDS16 packs both into one 32-bit word
-//                 (gamma low 16 bits, expiry relative to a rebased origin
-//                 high 16 bits), LDS32 keeps two 32-bit words (absolute
-//                 expiry)
-//   cg[v]         colour of v (low 16) | gamma[v][col v] (high 16)
-//   cmask         one bit per vertex: v is in conflict (gamma[v][col v] > 0)
-//   conf[]        the conflicting vertices, rebuilt from cmask after a move
+// Per individual (the search body and the table tiers are in tabu_body.h):
+//   tab[v*kp + c]  gamma[v][c] (neighbours of v coloured c) and the tabu
+//                  expiry of (v, c), rows padded to kp = k rounded up to 4;
+//                  LDS16 packs both into a 32-bit LDS word, LDS32 keeps two,
+//                  SPLIT16 / SPLIT8 keep 16- / 8-bit gamma in LDS and the
+//                  expiries in device memory, GLOBAL16 keeps the packed word
+//                  in device memory
+//   cg[v]          colour of v (low 16) | gamma[v][col v] (high 16)
+//   list, pos      the conflicting vertices (with tombstones), kept in place
 //
 // One iteration:
-//   scan      every thread takes candidates j = i*k + c (i-th conflicting
-//             vertex, colour c) strided by the block size and keeps its best
-//             admissible (delta, v, c) and how many tie with it;
-//   reduce    DPP wave minimum, cross-wave minimum through LDS; if several
-//             admissible moves share the minimum delta, the holders of those
-//             moves hash them (Philox of (ind, t, v, c)) and a second
-//             reduction picks the smallest (hash, v, c);
-//   apply     wave 0 updates the colour, tabu expiry, the gamma rows of the
-//             neighbours (CSR row of v* streamed from device memory), the
-//             conflict mask and list, f and the lazily kept best colouring.
+//   scan      every thread takes (list entry, colour quad) pairs strided by
+//             the block size and keeps its best admissible delta, the count
+//             of moves tied with it and the first two;
+//   wave      DPP minimum; the moves tied at the wave's minimum are hashed
+//             (Philox of (ind, t, v, c)) unless another wave already
+//             published a better delta;
+//   reduce    one barrier, then the (delta, hash, v, c) minimum over the
+//             waves' slots;
+//   apply     all threads update the gamma rows of v*'s neighbours (CSR row
+//             from device memory) and the conflict list; wave 0 writes the
+//             tabu entries, v*'s state and the lazily kept best colouring.
+//
+// The byte-gamma tier gives up on an individual whose colour classes would
+// pass 255 vertices; a rerun kernel repeats those from their start colouring
+// with the 16-bit device table, so every tier returns the same result.
 #include "tabu_body.h"
 
 namespace dlm {

@@ -49,7 +49,7 @@ struct WvcpArgs {
 // weight, frozen-until, 0}; per class {largest weight, its multiplicity,
 // second largest, 0} and the largest weights again as a dense vector.
 struct WvcpLayout {
-  uint32_t gam, vinfo, cls, m1v, bestg, red, stage, bytes;
+  uint32_t gam, vinfo, cls, m1v, bestg, red, stage, pub, bytes;
 };
 
 __host__ __device__ constexpr int wvcp_stride(int k) { return (k + 3) & ~3; }
@@ -72,6 +72,8 @@ __host__ __device__ inline WvcpLayout wvcp_layout(int n, int k, int nw) {
   o += 2u * 32u * nw;  // two parity buffers of 8 words per wave
   L.stage = o;
   o += nw * 4u * (kWStage + 4);
+  L.pub = o;  // best key published so far, by iteration parity
+  o += 16u;
   L.bytes = o;
   return L;
 }
@@ -117,12 +119,17 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
   int16_t* bestg = reinterpret_cast<int16_t*>(smem + L.bestg);
   uint32_t* red = reinterpret_cast<uint32_t*>(smem + L.red);  // [2][NW][8]
   uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);
+  unsigned long long* pub = reinterpret_cast<unsigned long long*>(smem + L.pub);
   int16_t* gcol = a.colors + (size_t)li * n;
   const Key key = a.key;
   const int32_t* __restrict__ col_idx = a.col_idx;
   __shared__ int32_t s_red[2 * NW];
 
   int bad = 0;
+  if (tid == 0) {
+    pub[0] = ~0ull;
+    pub[1] = ~0ull;
+  }
   for (int v = tid; v < n; v += BLOCK) {
     const int c = gcol[v];
     bad |= (c < 0) | (c >= k);
@@ -270,8 +277,25 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
       KT wbd;
       if constexpr (k32) wbd = wave_min_u32(bd);
       else wbd = wave_min_u64(bd);
+      // the wave's best key as dg + 2^62, whichever width the scan used
+      uint64_t wk64 = ~0ull;
+      if constexpr (k32) {
+        if (wbd != kNoKey) wk64 = (uint64_t)(int64_t)(int32_t)((uint32_t)wbd - 0x80000000u) + kGBias;
+      } else {
+        wk64 = wbd;
+      }
+      // publish it; a wave beaten by an earlier one cannot hold the chosen
+      // move and skips the hashing
+      bool live = wbd != kNoKey;
+      if (live) {
+        unsigned long long prev = 0ull;
+        if (lane == 0) prev = atomicMin(&pub[t & 1], (unsigned long long)wk64);
+        const uint64_t p64 = ((uint64_t)readlane((uint32_t)(prev >> 32), 0) << 32) | readlane((uint32_t)prev, 0);
+        live = p64 >= wk64;
+      }
       uint64_t hk = ~0ull;
-      if (wbd != kNoKey) {
+      uint32_t wcnt = 0u;
+      if (live) {
         auto hkey = [&](uint32_t idx) -> uint64_t {
           return ((uint64_t)philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key) << 32) | idx;
         };
@@ -281,6 +305,7 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
         const uint32_t nR = wave_sum_u32(Rr ? cnt : 0u);
         const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
         const uint32_t total = nA + nB + nR;
+        wcnt = total;
         auto rescan = [&](auto&& sink) {
           int i = i0, q = q0;
           for (int j = tid; j < totq; j += BLOCK) {
@@ -312,22 +337,14 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
         }
       }
       {
-        const uint64_t whk = wave_min_u64(hk);
-        const uint32_t wcnt = wave_sum_u32(bd == wbd ? cnt : 0u);
+        const uint64_t whk = live ? wave_min_u64(hk) : ~0ull;
         // the chosen vertex's colour and gamma, read while no wave writes them
         uint32_t wold = 0, wdcf = 0;
-        if (wbd != kNoKey) {
+        if (live) {
           const uint32_t v = (uint32_t)whk >> 16, c = (uint32_t)whk & 0xffffu;
           const uint32_t x = vinfo[v].x;
           wold = x & 0xffffu;
           wdcf = (uint32_t)((int32_t)gam[v * kp + (int)c] - (int32_t)(x >> 16));
-        }
-        // the slot holds the 64-bit key (dg + 2^62) whichever width the scan used
-        uint64_t wk64 = ~0ull;
-        if constexpr (k32) {
-          if (wbd != kNoKey) wk64 = (uint64_t)(int64_t)(int32_t)((uint32_t)wbd - 0x80000000u) + kGBias;
-        } else {
-          wk64 = wbd;
         }
         if (lane == 0) {
           uint32_t* e = red + (par + wid) * 8;
@@ -339,6 +356,8 @@ __global__ __launch_bounds__(BLOCK) void wvcp_kernel(WvcpArgs a) {
       if (k32_round) pick(0u);
       else pick(0ull);
       __syncthreads();
+      // every wave has published: the slot is free again for iteration t + 2
+      if (tid == 0) pub[t & 1] = ~0ull;
       // cross-wave: smallest (key, hash, v, c), folded in scalar registers
       auto rfl = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
       uint64_t gk, gh;
