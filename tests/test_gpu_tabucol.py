@@ -264,3 +264,16 @@ def test_gnp1000_k85_byte_table_and_auto(dlm, dev):
         say(f"tabu gnp1000 k=85 {table}")
         gpu = gpu_run(dlm, g, starts, k, T, 9, table=table, block=256)
         compare(gpu, ref, range(pop), f"gnp1000 {table}")
+
+
+def test_auto_table_and_block(dlm, dev):
+    """Table and block both automatic on G(1000, 0.5), k = 90: the byte table
+    fits one individual per CU, so 512 threads are used; results equal the
+    oracle's (the choice never changes a trajectory)."""
+    g = gnp(1000, 0.5, seed=0)
+    k, T, pop = 90, 3000, 5
+    starts = oracle.init_random(g.n, k, pop, seed=13)
+    ref = oracle.tabucol_batch(g, starts, np.arange(40, 40 + pop), k, T, seed=21)
+    say("tabu gnp1000 k=90 auto table, auto block")
+    gpu = gpu_run(dlm, g, starts, k, T, 21, ind_base=40)
+    compare(gpu, ref, range(pop), "gnp1000 auto/auto")
