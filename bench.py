@@ -146,7 +146,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for {args.gpus}); "
               "the population shards by individual with no communication between shards",
               file=sys.stderr)
         sys.exit(2)

@@ -36,7 +36,7 @@ extern "C" {
 #define DLM_E_INVAL (-1)       /* bad argument (null pointer, size, range, CSR rule) */
 #define DLM_E_NOMEM (-2)       /* device allocation failed */
 #define DLM_E_HIP (-3)         /* a HIP runtime call or kernel launch failed */
-#define DLM_E_UNSUPPORTED (-4) /* valid request beyond what this build supports */
+#define DLM_E_UNSUPPORTED (-4) /* valid request beyond what this library supports */
 
 #define DLM_NSTATS 8 /* per-individual counters written by the tabu calls */
 
@@ -307,7 +307,7 @@ int dlm_select(const float* scores_dev, int32_t count, int32_t keep, int32_t mod
 
 /* ------------------------------------------------------------------------
  * Device steps of one memetic generation (Algorithm 1) in the simplified
- * form of this build: random partner pairing, offspring gather, target
+ * form of this library: random partner pairing, offspring gather, target
  * standardisation for the scorer, and the (mu + lambda) population update
  * that stands in for the paper's distance-based update (Section 2.5).
  * ---------------------------------------------------------------------- */
