@@ -88,6 +88,16 @@ __device__ __forceinline__ uint32_t readlane(uint32_t x, int lane) {
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// median of three (one v_med3_u32)
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// number of lanes below the calling lane whose bit is set in m
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+}
+
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
   x = min(x, dpp_mov<dpp::kXor1>(x));
   x = min(x, dpp_mov<dpp::kXor2>(x));

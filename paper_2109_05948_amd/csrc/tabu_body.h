@@ -13,6 +13,7 @@ constexpr int kRebaseEvery = 16384;      // 16-bit expiries: the origin moves ev
 constexpr uint32_t kPadGamma = 0x7fffu;  // gamma stored in the padding colours k .. kp-1
 constexpr uint32_t kNone = 0xffffffffu;  // no admissible candidate
 constexpr int kStage = 64;               // tied moves a wave hashes in one staged pass
+constexpr int kKeyRounds = 16384;        // rounds per lane that 16-bit candidate numbers cover
 
 // Table encoding, common to every storage policy:
 //  * the entry (v, col v) of a vertex's current colour holds the expiry
@@ -55,6 +56,12 @@ struct TabLds16 {
     g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
     g[3] = x.w & 0xffffu; fr[3] = x.w <= thr;
   }
+  __device__ static __forceinline__ void eval4h(const Raw& x, uint32_t thr, uint32_t gh[4], bool fr[4]) {
+    gh[0] = x.x << 16; fr[0] = x.x <= thr;
+    gh[1] = x.y << 16; fr[1] = x.y <= thr;
+    gh[2] = x.z << 16; fr[2] = x.z <= thr;
+    gh[3] = x.w << 16; fr[3] = x.w <= thr;
+  }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) {
     reinterpret_cast<uint16_t*>(w)[2 * i + 1] = (uint16_t)ex;
   }
@@ -93,6 +100,10 @@ struct TabLds32 {
     g[0] = r.x.x; fr[0] = r.x.y <= thr; g[1] = r.x.z; fr[1] = r.x.w <= thr;
     g[2] = r.y.x; fr[2] = r.y.y <= thr; g[3] = r.y.z; fr[3] = r.y.w <= thr;
   }
+  __device__ static __forceinline__ void eval4h(const Raw& r, uint32_t thr, uint32_t gh[4], bool fr[4]) {
+    gh[0] = r.x.x << 16; fr[0] = r.x.y <= thr; gh[1] = r.x.z << 16; fr[1] = r.x.w <= thr;
+    gh[2] = r.y.x << 16; fr[2] = r.y.y <= thr; gh[3] = r.y.z << 16; fr[3] = r.y.w <= thr;
+  }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { w[2 * i + 1] = ex; }
   __device__ __forceinline__ void rebase(int) {}
 };
@@ -127,6 +138,12 @@ struct TabGlobal16 {
     g[1] = x.y & 0xffffu; fr[1] = x.y <= thr;
     g[2] = x.z & 0xffffu; fr[2] = x.z <= thr;
     g[3] = x.w & 0xffffu; fr[3] = x.w <= thr;
+  }
+  __device__ static __forceinline__ void eval4h(const Raw& x, uint32_t thr, uint32_t gh[4], bool fr[4]) {
+    gh[0] = x.x << 16; fr[0] = x.x <= thr;
+    gh[1] = x.y << 16; fr[1] = x.y <= thr;
+    gh[2] = x.z << 16; fr[2] = x.z <= thr;
+    gh[3] = x.w << 16; fr[3] = x.w <= thr;
   }
   // only the high half changes; the low half of row v* is not touched by this move
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { st(i, (ld(i) & 0xffffu) | (ex << 16)); }
@@ -183,6 +200,15 @@ struct TabSplit16 {
     fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
     fr[3] = (uint32_t)(t >> 48) <= thr;
   }
+  __device__ static __forceinline__ void eval4h(const Raw& r, uint32_t thr, uint32_t gh[4], bool fr[4]) {
+    const uint2 x = r.x;
+    const uint64_t t = r.t;
+    gh[0] = x.x << 16; gh[1] = x.x & 0xffff0000u; gh[2] = x.y << 16; gh[3] = x.y & 0xffff0000u;
+    fr[0] = ((uint32_t)t & 0xffffu) <= thr;
+    fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
+    fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
+    fr[3] = (uint32_t)(t >> 48) <= thr;
+  }
   __device__ __forceinline__ void set_tabu(int i, uint32_t ex) { tb[i] = (uint16_t)ex; }
   __device__ __forceinline__ void rebase(int i) {
     uint32_t e = ldt(i);
@@ -234,6 +260,17 @@ struct TabSplit8 {
     const uint32_t x = r.x;
     const uint64_t t = r.t;
     gg[0] = x & 0xffu; gg[1] = (x >> 8) & 0xffu; gg[2] = (x >> 16) & 0xffu; gg[3] = x >> 24;
+    fr[0] = ((uint32_t)t & 0xffffu) <= thr;
+    fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
+    fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
+    fr[3] = (uint32_t)(t >> 48) <= thr;
+  }
+  __device__ static __forceinline__ void eval4h(const Raw& r, uint32_t thr, uint32_t gh[4], bool fr[4]) {
+    const uint32_t x = r.x;
+    const uint64_t t = r.t;
+    // byte c of x into bits 16..23, zeros elsewhere (selector byte 0x0c reads as 0): one v_perm_b32 each
+#pragma unroll
+    for (int c = 0; c < 4; ++c) gh[c] = __builtin_amdgcn_perm(x, x, 0x0c000c0cu | ((uint32_t)c << 16));
     fr[0] = ((uint32_t)t & 0xffffu) <= thr;
     fr[1] = ((uint32_t)(t >> 16) & 0xffffu) <= thr;
     fr[2] = ((uint32_t)(t >> 32) & 0xffffu) <= thr;
@@ -472,6 +509,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   // quads (i, q): list entry i, colours 4q..4q+3; thread tid takes quads tid + s*BLOCK
   const int kq = kp >> 2;
   const int i0 = tid / kq, q0 = tid - (tid / kq) * kq, di = BLOCK / kq, dq = BLOCK - (BLOCK / kq) * kq;
+  const uint32_t kq_inv = 0xffffffffu / (uint32_t)kq;  // quotient by kq: one __umulhi and one correction
   auto step = [&](int& i, int& q) {
     q += dq;
     i += di;
@@ -503,119 +541,219 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
     if (wid == 0 && (t & 63) == 0)
       Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, key), ten_rand);
 
-    // ---- scan: best admissible biased delta, how many candidates share it,
-    // and the first two of them (move index (v << 16) | c)
-    uint32_t bd = kNone, cnt = 0, s0 = 0, s1 = 0;
-    auto consider = [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
-      const uint32_t bdv = g + boff;  // gamma[v][c] - gamma[v][col v] + kBias
-      const uint32_t b = (fr || (int)bdv <= aspb) ? bdv : kNone;
-      const bool lt = b < bd, eq = b == bd;
-      s1 = (eq && cnt == 1u) ? idx : s1;
-      cnt = lt ? 1u : cnt + (eq ? 1u : 0u);
-      s0 = lt ? idx : s0;
-      bd = lt ? b : bd;
-    };
-    auto do_quad = [&](int i, int q, auto&& fn) {
-      const uint32_t v = list[i];
-      uint32_t g4[4];
-      bool f4[4];
-      Tab::eval4(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), thr, g4, f4);
-      const uint32_t boff = (uint32_t)kBias - (cg[v] >> 16);
-      const uint32_t idx = (v << 16) | (uint32_t)(4 * q);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) fn(idx + r, g4[r], f4[r], boff);
-    };
+    // ---- scan.  Quad j (list entry j / kq, colours 4 (j % kq) .. +3) belongs
+    // to thread j % BLOCK, which reaches it in its round j / BLOCK.
     const int totq = len * kq;
-    {
-      int i = i0, q = q0, j = tid;
-      // two quads per round: their loads are independent and issue together
-      for (; j + BLOCK < totq; j += 2 * BLOCK) {
-        const int ia = i, qa = q;
-        step(i, q);
-        const int ib = i, qb = q;
-        step(i, q);
-        const uint32_t va = list[ia], vb = list[ib];
-        const typename Tab::Raw ra = tab.load4((int)__umul24(va, (uint32_t)kp) + 4 * qa);
-        const typename Tab::Raw rb = tab.load4((int)__umul24(vb, (uint32_t)kp) + 4 * qb);
-        const uint32_t ea = cg[va], eb = cg[vb];
-        uint32_t ga[4], gb[4];
-        bool fa[4], fb[4];
-        Tab::eval4(ra, thr, ga, fa);
-        Tab::eval4(rb, thr, gb, fb);
-        const uint32_t oa = (uint32_t)kBias - (ea >> 16), ob = (uint32_t)kBias - (eb >> 16);
-        const uint32_t xa = (va << 16) | (uint32_t)(4 * qa), xb = (vb << 16) | (uint32_t)(4 * qb);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) consider(xa + r, ga[r], fa[r], oa);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) consider(xb + r, gb[r], fb[r], ob);
-      }
-      if (j < totq) do_quad(i, q, consider);
-    }
-
-    // ---- wave result: smallest (biased delta, Philox word, v, c).  The
-    // moves tied at the wave's best delta are hashed now, before the
-    // cross-wave step, so one barrier settles the iteration.  They are first
-    // gathered in LDS (two per lane from registers, more by a rescan of the
-    // lane's quads) so that one Philox evaluation per lane covers up to 64.
-    const uint32_t wbd = wave_min_u32(bd);
+    uint32_t wbd;
+    bool live;
+    uint64_t hk = ~0ull;
+    uint32_t wcnt = 0u;  // moves of this wave at its best delta
+    uint32_t* stg = stage + wid * (kStage + 4);
     // publish the wave's best delta; a wave beaten by an earlier one cannot
     // hold the chosen move and skips the hashing
-    bool live = wbd != kNone;
-    if (live) {
-      uint32_t prev = 0u;
-      if (lane == 0) prev = atomicMin(&sc[2 + (t & 1)], wbd);
-      live = readlane(prev, 0) >= wbd;
-    }
-    uint64_t hk = ~0ull;
-    uint32_t wcnt = 0u;
-    if (live) {
-      auto hkey = [&](uint32_t idx) -> uint64_t {
-        const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key);
-        return ((uint64_t)h << 32) | idx;
+    auto publish = [&](uint32_t w) {
+      bool lv = w != kNone;
+      if (lv) {
+        uint32_t prev = 0u;
+        if (lane == 0) prev = atomicMin(&sc[2 + (t & 1)], w);
+        lv = readlane(prev, 0) >= w;
+      }
+      return lv;
+    };
+    auto hkey = [&](uint32_t idx) -> uint64_t {
+      const uint32_t h = philox_w0(ind, (uint32_t)t, idx >> 16, idx & 0xffffu, key);
+      return ((uint64_t)h << 32) | idx;
+    };
+    // The moves tied at the wave's best delta are hashed before the
+    // cross-wave step, so one barrier settles the iteration.  They are first
+    // gathered in LDS so that one Philox evaluation per lane covers up to
+    // kStage of them.
+    auto hash_staged = [&](uint32_t total) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t c0 = 0; c0 < total; c0 += kWave)
+        if (c0 + lane < total) hk = umin64(hk, hkey(stg[c0 + lane]));
+    };
+    if (totq <= kKeyRounds * BLOCK) {
+      // Candidate keys: biased delta << 16 | (4 * round + r), r the colour
+      // within the quad.  A key names one candidate of the lane and orders
+      // the candidates by delta; each lane keeps its three smallest
+      // admissible keys (a v_min and two v_med3 per candidate).
+      const uint32_t aspk = aspb >= 0 ? ((uint32_t)aspb + 1u) << 16 : 0u;  // key < aspk <=> biased delta <= aspb
+      uint32_t m1 = kNone, m2 = kNone, m3 = kNone;
+      auto keys = [&](const typename Tab::Raw& raw, uint32_t e, uint32_t r4, auto&& fn) {
+        uint32_t g4[4];
+        bool f4[4];
+        Tab::eval4h(raw, thr, g4, f4);
+        uint32_t x = (((uint32_t)kBias - (e >> 16)) << 16) + r4;
+        asm("" : "+v"(x));  // one offset per quad: each key is then a single v_add3_u32
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t kk = g4[r] + x + (uint32_t)r;
+          fn(r, kk, f4[r] | (kk < aspk));
+        }
       };
-      auto is_tie = [&](uint32_t g, bool fr, uint32_t boff) {
-        const uint32_t bdv = g + boff;
-        return (fr || (int)bdv <= aspb) && bdv == wbd;
+      auto keep = [&](int, uint32_t kk, bool adm) {
+        const uint32_t y = adm ? kk : kNone;
+        m3 = umed3(m2, y, m3);
+        m2 = umed3(m1, y, m2);
+        m1 = min(m1, y);
       };
-      const bool tie = bd == wbd;
-      const bool A = tie && cnt <= 2u, B = tie && cnt == 2u, R = tie && cnt > 2u;
-      const uint64_t mA = __ballot(A), mB = __ballot(B);
-      const uint32_t nR = wave_sum_u32(R ? cnt : 0u);
-      const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
-      const uint32_t total = nA + nB + nR;
-      wcnt = total;  // every move of this wave at its best delta
-      if (total <= (uint32_t)kStage) {
-        uint32_t* stg = stage + wid * (kStage + 4);
-        uint32_t* rctr = stg + kStage;
-        if (lane == 0) *rctr = nA + nB;
-        if (A) stg[__builtin_amdgcn_mbcnt_hi((uint32_t)(mA >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mA, 0u))] = s0;
-        if (B) stg[nA + __builtin_amdgcn_mbcnt_hi((uint32_t)(mB >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mB, 0u))] = s1;
-        if (R) {
-          uint32_t p = atomicAdd(rctr, cnt);
+      {
+        int i = i0, q = q0, j = tid;
+        uint32_t r4 = 0;
+        // two quads per round: their loads are independent and issue together
+        for (; j + BLOCK < totq; j += 2 * BLOCK, r4 += 8) {
+          const int ia = i, qa = q;
+          step(i, q);
+          const int ib = i, qb = q;
+          step(i, q);
+          const uint32_t va = list[ia], vb = list[ib];
+          const typename Tab::Raw ra = tab.load4((int)__umul24(va, (uint32_t)kp) + 4 * qa);
+          const typename Tab::Raw rb = tab.load4((int)__umul24(vb, (uint32_t)kp) + 4 * qb);
+          const uint32_t ea = cg[va], eb = cg[vb];
+          keys(ra, ea, r4, keep);
+          keys(rb, eb, r4 + 4, keep);
+        }
+        if (j < totq) {
+          const uint32_t v = list[i];
+          keys(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), cg[v], r4, keep);
+        }
+      }
+      const uint32_t wmin = wave_min_u32(m1);
+      wbd = wmin == kNone ? kNone : wmin >> 16;
+      live = publish(wbd);
+      if (live) {
+        // a lane with one or two ties names them from its keys; a lane with
+        // three or more lists all of its ties by a rescan of its quads
+        auto move_of = [&](uint32_t kk) {  // key of this lane -> move (v << 16) | c
+          const uint32_t jj = (uint32_t)tid + ((kk & 0xffffu) >> 2) * (uint32_t)BLOCK;
+          uint32_t ii = __umulhi(jj, kq_inv), qq = jj - ii * (uint32_t)kq;
+          if (qq >= (uint32_t)kq) {
+            qq -= (uint32_t)kq;
+            ++ii;
+          }
+          return ((uint32_t)list[ii] << 16) | (4u * qq + (kk & 3u));
+        };
+        const bool R = (m3 >> 16) == wbd;
+        const bool A = !R && (m1 >> 16) == wbd, B = !R && (m2 >> 16) == wbd;
+        const uint32_t xa = A ? move_of(m1) : 0u, xb = B ? move_of(m2) : 0u;
+        const uint64_t mA = __ballot(A), mB = __ballot(B), mR = __ballot(R);
+        const uint32_t nA = (uint32_t)__popcll(mA);
+        uint32_t total = nA + (uint32_t)__popcll(mB);
+        if (A) stg[lane_rank(mA)] = xa;
+        if (B && nA + lane_rank(mB) < (uint32_t)kStage) stg[nA + lane_rank(mB)] = xb;
+        // every tie of the lanes in R, round by round over the wave's quads
+        auto rescan = [&](auto&& fn) {
           int i = i0, q = q0;
-          for (int j = tid; j < totq; j += BLOCK) {
-            do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
-              if (is_tie(g, fr, boff)) stg[p++] = idx;
-            });
+          for (int j0 = wid * kWave; j0 < totq; j0 += BLOCK) {  // uniform over the wave
+            bool tie[4] = {false, false, false, false};
+            uint32_t mv = 0u;
+            if (R && j0 + lane < totq) {
+              const uint32_t v = list[i];
+              mv = (v << 16) | (uint32_t)(4 * q);
+              keys(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), cg[v], 0u,
+                   [&](int r, uint32_t kk, bool adm) { tie[r] = adm && (kk >> 16) == wbd; });
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) fn(tie[r], mv + (uint32_t)r);
             step(i, q);
           }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t c0 = 0; c0 < total; c0 += kWave)
-          if (c0 + lane < total) hk = umin64(hk, hkey(stg[c0 + lane]));
-      } else {
-        // too many ties to stage: every lane hashes its own
-        if (A) hk = hkey(s0);
-        if (B) hk = umin64(hk, hkey(s1));
-        if (R) {
-          int i = i0, q = q0;
-          for (int j = tid; j < totq; j += BLOCK) {
-            do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
-              if (is_tie(g, fr, boff)) hk = umin64(hk, hkey(idx));
+        };
+        if (mR != 0)
+          rescan([&](bool tie, uint32_t mv) {
+            const uint64_t m = __ballot(tie);
+            const uint32_t p = total + lane_rank(m);
+            if (tie && p < (uint32_t)kStage) stg[p] = mv;
+            total += (uint32_t)__popcll(m);
+          });
+        wcnt = total;
+        if (total <= (uint32_t)kStage) {
+          hash_staged(total);
+        } else {
+          // too many ties to stage: every lane hashes its own
+          if (A) hk = hkey(xa);
+          if (B) hk = umin64(hk, hkey(xb));
+          if (mR != 0)
+            rescan([&](bool tie, uint32_t mv) {
+              if (tie) hk = umin64(hk, hkey(mv));
             });
-            step(i, q);
+        }
+      }
+    } else {
+      // More rounds than 16-bit candidate numbers cover: each lane keeps its
+      // best biased delta, the count of candidates at it and the first two
+      // (move index (v << 16) | c).
+      uint32_t bd = kNone, cnt = 0, s0 = 0, s1 = 0;
+      auto consider = [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+        const uint32_t bdv = g + boff;  // gamma[v][c] - gamma[v][col v] + kBias
+        const uint32_t b = (fr || (int)bdv <= aspb) ? bdv : kNone;
+        const bool lt = b < bd, eq = b == bd;
+        s1 = (eq && cnt == 1u) ? idx : s1;
+        cnt = lt ? 1u : cnt + (eq ? 1u : 0u);
+        s0 = lt ? idx : s0;
+        bd = lt ? b : bd;
+      };
+      auto do_quad = [&](int i, int q, auto&& fn) {
+        const uint32_t v = list[i];
+        uint32_t g4[4];
+        bool f4[4];
+        Tab::eval4(tab.load4((int)__umul24(v, (uint32_t)kp) + 4 * q), thr, g4, f4);
+        const uint32_t boff = (uint32_t)kBias - (cg[v] >> 16);
+        const uint32_t idx = (v << 16) | (uint32_t)(4 * q);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fn(idx + r, g4[r], f4[r], boff);
+      };
+      {
+        int i = i0, q = q0;
+        for (int j = tid; j < totq; j += BLOCK) {
+          do_quad(i, q, consider);
+          step(i, q);
+        }
+      }
+      wbd = wave_min_u32(bd);
+      live = publish(wbd);
+      if (live) {
+        auto is_tie = [&](uint32_t g, bool fr, uint32_t boff) {
+          const uint32_t bdv = g + boff;
+          return (fr || (int)bdv <= aspb) && bdv == wbd;
+        };
+        const bool tie = bd == wbd;
+        const bool A = tie && cnt <= 2u, B = tie && cnt == 2u, R = tie && cnt > 2u;
+        const uint64_t mA = __ballot(A), mB = __ballot(B);
+        const uint32_t nR = wave_sum_u32(R ? cnt : 0u);
+        const uint32_t nA = (uint32_t)__popcll(mA), nB = (uint32_t)__popcll(mB);
+        const uint32_t total = nA + nB + nR;
+        wcnt = total;
+        if (total <= (uint32_t)kStage) {
+          uint32_t* rctr = stg + kStage;
+          if (lane == 0) *rctr = nA + nB;
+          if (A) stg[lane_rank(mA)] = s0;
+          if (B) stg[nA + lane_rank(mB)] = s1;
+          if (R) {
+            uint32_t p = atomicAdd(rctr, cnt);
+            int i = i0, q = q0;
+            for (int j = tid; j < totq; j += BLOCK) {
+              do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+                if (is_tie(g, fr, boff)) stg[p++] = idx;
+              });
+              step(i, q);
+            }
+          }
+          hash_staged(total);
+        } else {
+          // too many ties to stage: every lane hashes its own
+          if (A) hk = hkey(s0);
+          if (B) hk = umin64(hk, hkey(s1));
+          if (R) {
+            int i = i0, q = q0;
+            for (int j = tid; j < totq; j += BLOCK) {
+              do_quad(i, q, [&](uint32_t idx, uint32_t g, bool fr, uint32_t boff) {
+                if (is_tie(g, fr, boff)) hk = umin64(hk, hkey(idx));
+              });
+              step(i, q);
+            }
           }
         }
       }

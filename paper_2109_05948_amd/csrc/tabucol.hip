@@ -13,8 +13,9 @@
 //
 // One iteration:
 //   scan      every thread takes (list entry, colour quad) pairs strided by
-//             the block size and keeps its best admissible delta, the count
-//             of moves tied with it and the first two;
+//             the block size and keeps its three smallest admissible
+//             candidate keys (biased delta << 16 | the thread's candidate
+//             number);
 //   wave      DPP minimum; the moves tied at the wave's minimum are hashed
 //             (Philox of (ind, t, v, c)) unless another wave already
 //             published a better delta;

@@ -277,3 +277,22 @@ def test_auto_table_and_block(dlm, dev):
     say("tabu gnp1000 k=90 auto table, auto block")
     gpu = gpu_run(dlm, g, starts, k, T, 21, ind_base=40)
     compare(gpu, ref, range(pop), "gnp1000 auto/auto")
+
+
+@pytest.mark.parametrize("block", [64, 128, 1024])
+def test_many_rounds_per_lane(dlm, dev, block):
+    """A perfect matching on 3000 vertices, all of colour 0, k = 2000: every
+    vertex conflicts and every recolouring ties at delta -1 (millions of tied
+    moves per iteration).  3000 x 500 colour quads give a 64-thread
+    workgroup more rounds per lane (23,438) than 16-bit candidate numbers
+    cover, so it takes the count-and-first-two scan; 128 and 1024 threads
+    take the key scan with candidate numbers up to 46,876 and 5,860."""
+    from workloads.graphs import from_edges
+    n, k, T, pop = 3000, 2000, 30, 2
+    g = from_edges(n, np.array([(2 * i, 2 * i + 1) for i in range(n // 2)], np.int64), "matching3000")
+    starts = np.zeros((pop, n), np.int16)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=5)
+    assert (ref["stats"][:, 4] == T).all()  # every iteration had tied moves
+    say(f"tabu matching3000 k=2000 block={block} global16")
+    gpu = gpu_run(dlm, g, starts, k, T, 5, table="global16", block=block)
+    compare(gpu, ref, range(pop), f"matching3000 block={block}")
