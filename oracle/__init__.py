@@ -6,7 +6,9 @@ does.  It shares no code with the HIP kernels.
 
 ``oracle.c`` holds the search algorithms (plain C, built with gcc);
 ``scorer.py`` the FP64 numpy reference of the offspring scorer;
-``brute.py`` exhaustive solvers for tiny graphs used as pins.
+``brute.py`` exhaustive solvers for tiny graphs used as pins;
+``diversity.py`` the partition distance, spacing update and nearest
+neighbours of the population (plain Python).
 """
 from __future__ import annotations
 
