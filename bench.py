@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
-                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer"])
+                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity"])
     ap.add_argument("--cutoff", type=float, default=300.0,
                     help="memetic1000: wall-clock limit per loop (seconds)")
     ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
@@ -170,6 +170,8 @@ def main():
 
     if args.workload == "scorer":
         return bench_scorer(args, workload("memetic1000"), dlm, torch)
+    if args.workload == "diversity":
+        return bench_diversity(args, workload("gnp500"), dlm, torch)
     w = workload(args.workload)
     if args.workload == "uneven64":
         return bench_uneven(args, w, dlm, torch)
@@ -425,6 +427,80 @@ def bench_scorer(args, w, dlm, torch):
            "roofline_mfma": {"bound": "mfma", "achieved": mfma_f / (inf_ms * 1e-3) / 1e12, "peak": 2500.0,
                              "unit": "TFLOP/s", "frac": mfma_f / (inf_ms * 1e-3) / 1e12 / 2500.0,
                              "train_achieved": tr_tflops}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_diversity(args, w, dlm, torch):
+    """One generation's diversity step at the G(500, 0.5), k = 49 shape with
+    8192 individuals: the old x new and new x new partition distances
+    written into the pool matrix (100.6 M pairs), the spacing update of the
+    16,384-member pool (spacing |V| / 10), the gather of the survivors'
+    distances and rows, and the 16 nearest neighbours of every survivor.
+    Inputs are two Philox-random populations and their conflict counts,
+    resident before timing.
+
+    The distance kernel is bound by issue (integer ALU): per pair, the
+    algorithmic work is n overlap increments plus two greedy passes of at
+    most k steps over k classes, n + 2 k^2 operations."""
+    g, k = w.graphs[0], w.k[0]
+    n, p = g.n, args.pop or w.pop
+    G = dlm.Graph.from_csr(g)
+    old, _ = dlm.init_population(G, k, p, seed=21)
+    new, _ = dlm.init_population(G, k, p, seed=22)
+    f_old, _ = dlm.evaluate(G, old, k)
+    f_new, _ = dlm.evaluate(G, new, k)
+    pools = [torch.zeros((2 * p, 2 * p), dtype=torch.int32, device="cuda") for _ in range(2)]
+    dlm.partition_distance(old, k, out=pools[0][:p, :p])  # the carried old x old block
+    stream = torch.cuda.current_stream()
+    spacing, K = n // 10, 16
+    pairs = p * p + p * (p - 1) // 2
+
+    def step(ev=None):
+        pool, nxt = pools[0], pools[1]
+        if ev:
+            ev[0].record(stream)
+        dlm.partition_distance(old, k, new, out=pool[:p, p:])
+        dlm.partition_distance(new, k, out=pool[p:, p:])
+        if ev:
+            ev[1].record(stream)
+        pick, nsp = dlm.spacing_update(f_old, f_new, pool, p, spacing)
+        if ev:
+            ev[2].record(stream)
+        dlm.gather_distances(pool, pick, out=nxt[:p, :p])
+        rows, fs = dlm.gather_pool(old, f_old, new, f_new, pick)
+        nn = dlm.nearest(nxt, K, p=p)
+        if ev:
+            ev[3].record(stream)
+        return nsp, nn
+
+    for s_ in range(args.warmup):
+        log(f"warmup step {s_}")
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        nsp, _ = step(ev[s_])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dist_ms = float(np.mean([a.elapsed_time(b) for a, b, _, _ in ev]))
+    upd_ms = float(np.mean([b.elapsed_time(c) for _, b, c, _ in ev]))
+    rest_ms = float(np.mean([c.elapsed_time(d) for _, _, c, d in ev]))
+    ops = float(pairs) * (n + 2 * k * k)
+    tops = ops / (dist_ms * 1e-3) / 1e12
+    log(f"timed {args.steps} steps in {dt:.3f} s; distances {dist_ms:.1f} ms, spacing update {upd_ms:.1f} ms, "
+        f"gathers + nearest {rest_ms:.1f} ms; {int(nsp.item())} of {p} taken under the spacing")
+    out = {"metric": "partition distances/s (population diversity step)", "value": pairs / (dist_ms * 1e-3),
+           "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "diversity", "graph": "G(n=500, p=0.5) seed 0", "k": k, "population": p,
+                      "pairs": pairs, "spacing": spacing, "nearest": K},
+           "distance_ms": dist_ms, "spacing_update_ms": upd_ms, "gather_nearest_ms": rest_ms,
+           "n_spaced": int(nsp.item()),
+           "roofline": {"bound": "alu", "achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                        "frac": tops / ALU_PEAK_TOPS, "traffic": None, "kernel": "distance_kernel",
+                        "ops_per_pair": n + 2 * k * k}}
     print(json.dumps(out), flush=True)
 
 

@@ -336,6 +336,72 @@ int dlm_pop_update(const int16_t* parents_dev, const int32_t* f_parents_dev,
                    void* stream);
 
 /* ------------------------------------------------------------------------
+ * Distance-based population management (Sections 2.4 to 2.6): the
+ * approximate partition distance, the population update under a minimum
+ * spacing, and the K nearest neighbours for parent matching.  A pool's
+ * distances live in one int32 matrix (row stride ld); the update and the
+ * gather read only its strict upper triangle, so the blocks of a new
+ * generation can be written straight into it (old x new by the block form,
+ * new x new by the triangle form, old x old gathered from the last pool).
+ * ---------------------------------------------------------------------- */
+
+/* Approximate set-theoretic partition distance (Section 2.4) of every pair
+ * (row i of a, row j of b):
+ *   M[c][d] = |{v : a_i[v] = c and b_j[v] = d}|;
+ *   S_ab: the classes of a_i by decreasing size (ties by index) each take the
+ *         free class of b_j with the largest positive M (ties by index);
+ *   S_ba: the same with a_i and b_j swapped;
+ *   out_dev[i * ld + j] = n - max(S_ab, S_ba).
+ * An upper bound of the exact distance (n - a maximum matching on M), equal
+ * to it on close partitions.
+ *   a_dev, b_dev  int16 device colourings [na][n], [nb][n], colours in [0, k);
+ *                 a pair with a colour outside [0, k) gets -1
+ *   tri           0: all na x nb pairs; 1: a_dev == b_dev and na == nb, the
+ *                 pairs i < j, mirrored below the diagonal, diagonal 0
+ *   out_dev       int32, row stride ld >= nb elements
+ *   workspace_dev caller-owned scratch of 2 (k + 2) (na + nb) bytes (the
+ *                 class orders)
+ * 1 <= n <= 32767, 1 <= k <= 256.  DLM_E_INVAL on bad sizes or null buffers. */
+int dlm_partition_distance(int32_t n, int32_t k, const int16_t* a_dev, int32_t na, const int16_t* b_dev,
+                           int32_t nb, int32_t tri, int32_t* out_dev, int64_t ld, void* workspace_dev,
+                           void* stream);
+
+/* Distance-and-quality population update (Section 2.5).  The pool is fa
+ * (indices 0..na-1) then fb (na..na+nb-1), lower score better.  Taken in
+ * order of (score, index), a member joins when its distance to every
+ * member already taken is > spacing (the paper's |V| / 10); if the pool
+ * runs out first, the best members left out fill the places.
+ *   dist_dev      int32 pool distances; only [lo * ld + hi], lo < hi, is read
+ *   pick_dev      int32 [keep] output: pool indices in the order taken
+ *   n_spaced_dev  int32 [1] output: how many were taken under the spacing
+ *   workspace_dev caller-owned scratch of 4 (na + nb) bytes
+ * na + nb <= 65536, 0 <= keep <= na + nb, ld >= na + nb.  One workgroup
+ * walks the pool (one barrier per member examined). */
+int dlm_spacing_update(const int32_t* fa_dev, int32_t na, const int32_t* fb_dev, int32_t nb,
+                       const int32_t* dist_dev, int64_t ld, int32_t keep, int32_t spacing,
+                       int32_t* pick_dev, int32_t* n_spaced_dev, void* workspace_dev, void* stream);
+
+/* out_dev[a * ld_out + b] = dist_dev[lo * ld + hi], lo / hi the smaller /
+ * larger of idx[a], idx[b], and 0 for a = b: the distances of the members a
+ * pick keeps, as a full symmetric count x count matrix. */
+int dlm_gather_distances(const int32_t* dist_dev, int64_t ld, const int32_t* idx_dev, int32_t count,
+                         int32_t* out_dev, int64_t ld_out, void* stream);
+
+/* Rows and scores of picked pool members: row r of out_dev (int16 [count][n])
+ * and fout_dev[r] come from member pick[r] (a row of ra_dev / fa_dev below
+ * na, else of rb_dev / fb_dev); an index outside [0, na + nb) gives a row of
+ * -1 and score -1. */
+int dlm_gather_pool(const int16_t* ra_dev, const int32_t* fa_dev, int32_t na, const int16_t* rb_dev,
+                    const int32_t* fb_dev, int32_t nb, int32_t n, const int32_t* pick_dev, int32_t count,
+                    int16_t* out_dev, int32_t* fout_dev, void* stream);
+
+/* K-nearest-neighbour parent matching (Section 2.6): nn_dev[i * K + t] is
+ * the t-th nearest j != i by dist_dev[i * ld + j] (a full symmetric p x p
+ * matrix), ties by smaller j.  0 <= K <= p - 1, p <= 65536, distances in
+ * [0, 65535]. */
+int dlm_nearest(const int32_t* dist_dev, int64_t ld, int32_t p, int32_t K, int32_t* nn_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * Offspring scorer (Section 2.3): a colour-permutation-invariant regressor
  * of the post-search score, trained online with Adam on (start colouring,
  * score after tabu search) pairs, and used by eq. (select_cross) to rank

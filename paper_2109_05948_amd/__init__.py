@@ -12,7 +12,12 @@ from ._abi import (  # noqa: F401
     Scorer,
     abi_version,
     evaluate,
+    gather_distances,
+    gather_pool,
     gather_rows,
+    nearest,
+    partition_distance,
+    spacing_update,
     pop_update,
     probe_lds_bandwidth,
     random_pairs,

@@ -33,6 +33,8 @@ EXPORTS = [
     "dlm_gather_rows", "dlm_standardize", "dlm_random_pairs", "dlm_pop_update",
     "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
     "dlm_multi_plan_destroy", "dlm_multi_autotune", "dlm_probe_lds_bandwidth",
+    "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
+    "dlm_nearest",
 ]
 
 
@@ -87,6 +89,11 @@ def lib():
             L.dlm_multi_plan_destroy.argtypes = [P]
             L.dlm_multi_autotune.argtypes = [P, I32, I32, P, P, P]
             L.dlm_probe_lds_bandwidth.argtypes = [I32, C.POINTER(C.c_double), P]
+            L.dlm_partition_distance.argtypes = [I32, I32, P, I32, P, I32, I32, P, I64, P, P]
+            L.dlm_spacing_update.argtypes = [P, I32, P, I32, P, I64, I32, I32, P, P, P, P]
+            L.dlm_gather_distances.argtypes = [P, I64, P, I32, P, I64, P]
+            L.dlm_gather_pool.argtypes = [P, P, I32, P, P, I32, I32, P, I32, P, P, P]
+            L.dlm_nearest.argtypes = [P, I64, I32, I32, P, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -398,6 +405,87 @@ def pop_update(parents: torch.Tensor, f_parents: torch.Tensor, offspring: torch.
                                                   _ptr(f_offspring), pop, n, _ptr(out), _ptr(f_out),
                                                   _ptr(ws), _stream(stream)))
     return out, f_out
+
+
+def partition_distance(a: torch.Tensor, k: int, b: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                       stream=None):
+    """dlm_partition_distance -> int32 [len(a), len(b)]; b None: the
+    triangle form over the rows of a (symmetric, zero diagonal).  ``out`` may
+    be a row-strided view (e.g. a block of a pool matrix)."""
+    _dev(a, torch.int16, "a")
+    tri = b is None
+    b = a if tri else b
+    _dev(b, torch.int16, "b")
+    if a.dim() != 2 or b.dim() != 2 or a.shape[1] != b.shape[1]:
+        raise ValueError("a and b must be [rows, n] with the same n")
+    na, nb, n = a.shape[0], b.shape[0], a.shape[1]
+    if out is None:
+        out = torch.empty((na, nb), dtype=torch.int32, device=a.device)
+    if out.dtype != torch.int32 or out.shape != (na, nb) or out.stride(1) != 1:
+        raise ValueError(f"out must be int32 [{na}, {nb}] with unit column stride")
+    ws = torch.empty(((k + 2) * (na + nb) + 1) // 2 + 1, dtype=torch.int32, device=a.device)
+    _check("dlm_partition_distance", lib().dlm_partition_distance(
+        n, k, _ptr(a), na, _ptr(b), nb, 1 if tri else 0, _ptr(out), out.stride(0), _ptr(ws), _stream(stream)))
+    return out
+
+
+def spacing_update(fa: torch.Tensor, fb: torch.Tensor, dist: torch.Tensor, keep: int, spacing: int,
+                   stream=None):
+    """dlm_spacing_update -> (pick int32 [keep], n_spaced int32 [1]); dist is
+    the pool's [na + nb, >= na + nb] matrix (its upper triangle is read)."""
+    _dev(fa, torch.int32, "fa")
+    _dev(fb, torch.int32, "fb")
+    _dev(dist, torch.int32, "dist")
+    total = fa.shape[0] + fb.shape[0]
+    if dist.shape[0] < total or dist.shape[1] < total or dist.stride(1) != 1:
+        raise ValueError(f"dist must cover the pool of {total}")
+    pick = torch.empty(keep, dtype=torch.int32, device=fa.device)
+    nsp = torch.empty(1, dtype=torch.int32, device=fa.device)
+    ws = torch.empty(max(total, 1), dtype=torch.int32, device=fa.device)
+    _check("dlm_spacing_update", lib().dlm_spacing_update(
+        _ptr(fa), fa.shape[0], _ptr(fb), fb.shape[0], _ptr(dist), dist.stride(0), keep, spacing, _ptr(pick),
+        _ptr(nsp), _ptr(ws), _stream(stream)))
+    return pick, nsp
+
+
+def gather_distances(dist: torch.Tensor, idx: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """dlm_gather_distances -> int32 [len(idx), len(idx)] (may be a strided view)."""
+    _dev(dist, torch.int32, "dist")
+    _dev(idx, torch.int32, "idx")
+    c = idx.shape[0]
+    out = out if out is not None else torch.empty((c, c), dtype=torch.int32, device=dist.device)
+    if out.shape != (c, c) or out.stride(1) != 1:
+        raise ValueError(f"out must be [{c}, {c}] with unit column stride")
+    _check("dlm_gather_distances", lib().dlm_gather_distances(
+        _ptr(dist), dist.stride(0), _ptr(idx), c, _ptr(out), out.stride(0), _stream(stream)))
+    return out
+
+
+def gather_pool(ra: torch.Tensor, fa: torch.Tensor, rb: torch.Tensor, fb: torch.Tensor, pick: torch.Tensor,
+                stream=None):
+    """dlm_gather_pool -> (rows int16 [len(pick), n], scores int32 [len(pick)])."""
+    for t, nm in ((ra, "ra"), (rb, "rb")):
+        _dev(t, torch.int16, nm)
+    for t, nm in ((fa, "fa"), (fb, "fb"), (pick, "pick")):
+        _dev(t, torch.int32, nm)
+    n = ra.shape[1]
+    out = torch.empty((pick.shape[0], n), dtype=torch.int16, device=ra.device)
+    fout = torch.empty(pick.shape[0], dtype=torch.int32, device=ra.device)
+    _check("dlm_gather_pool", lib().dlm_gather_pool(
+        _ptr(ra), _ptr(fa), ra.shape[0], _ptr(rb), _ptr(fb), rb.shape[0], n, _ptr(pick), pick.shape[0],
+        _ptr(out), _ptr(fout), _stream(stream)))
+    return out, fout
+
+
+def nearest(dist: torch.Tensor, K: int, p: int | None = None, stream=None):
+    """dlm_nearest -> int32 [p, K] (p defaults to dist.shape[0])."""
+    _dev(dist, torch.int32, "dist")
+    p = dist.shape[0] if p is None else p
+    if dist.stride(1) != 1:
+        raise ValueError("dist must have unit column stride")
+    out = torch.empty((p, K), dtype=torch.int32, device=dist.device)
+    _check("dlm_nearest", lib().dlm_nearest(_ptr(dist), dist.stride(0), p, K, _ptr(out), _stream(stream)))
+    return out
 
 
 class MultiItem(C.Structure):

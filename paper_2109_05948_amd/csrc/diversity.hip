@@ -1,0 +1,400 @@
+// Distance-based population management (Sections 2.4 to 2.6 of the paper):
+// the approximate set-theoretic partition distance between colourings, the
+// quality-ordered population update under a minimum spacing, and the K
+// nearest neighbours used for parent matching.
+//
+// Partition distance.  For colourings A and B of the same n vertices,
+// M[c][d] = |A_c & B_d|.  One greedy pass takes the classes of A by
+// decreasing size (ties by index) and gives each the free class of B with
+// the largest positive overlap (ties by index); a second pass swaps the
+// roles; D~ = n - the larger matched total.  Both passes are matchings, so
+// D~ is an upper bound of the exact distance (n - a maximum matching), and
+// it is exact on close partitions.
+//
+// One wave per pair: the k x k overlap counts are 16-bit halves of 32-bit
+// LDS words (k^2 / 2 words per wave), filled by one LDS atomic per vertex.
+// A greedy step is one LDS read per owned column (lane c owns classes c,
+// c + 64, ...) and a DPP wave maximum of (overlap << 16 | 0xffff - class);
+// the two passes run interleaved, as two independent chains.  The class
+// orders are computed once per colouring by a small kernel first.
+#include "dlm_common.h"
+
+namespace dlm {
+
+constexpr int kMaxDistK = 256;
+
+// rec[r] = int16[k + 2]: the classes of row r by decreasing size (ties by
+// index), then the number of non-empty classes, or -1 there when a colour
+// of the row lies outside [0, k).
+__global__ __launch_bounds__(64) void class_order_kernel(const int16_t* __restrict__ rows, int32_t n, int32_t k,
+                                                         int16_t* __restrict__ rec) {
+  __shared__ uint32_t size[kMaxDistK];
+  const int lane = threadIdx.x;
+  const int16_t* row = rows + (size_t)blockIdx.x * n;
+  for (int c = lane; c < k; c += kWave) size[c] = 0u;
+  __syncthreads();
+  uint32_t bad = 0u;
+  for (int v = lane; v < n; v += kWave) {
+    const int c = row[v];
+    if (c < 0 || c >= k)
+      bad = 1u;
+    else
+      atomicAdd(&size[c], 1u);
+  }
+  __syncthreads();
+  int16_t* out = rec + (size_t)blockIdx.x * (k + 2);
+  uint32_t nonempty = 0u;
+  for (int c = lane; c < k; c += kWave) {
+    const uint32_t sc = size[c];
+    uint32_t rank = 0u;
+    for (int d = 0; d < k; ++d) {
+      const uint32_t sd = size[d];
+      rank += (sd > sc) || (sd == sc && d < c);
+    }
+    out[rank] = (int16_t)c;
+    nonempty += sc > 0u;
+  }
+  nonempty = wave_sum_u32(nonempty);
+  bad = wave_max_u32(bad);
+  if (lane == 0) {
+    out[k] = bad ? (int16_t)-1 : (int16_t)nonempty;
+    out[k + 1] = 0;
+  }
+}
+
+// words of one wave's overlap table, a multiple of 4 (cleared with 16-byte stores)
+__host__ __device__ inline uint32_t hist_words(int k) { return (((uint32_t)(k * k) + 1u) / 2u + 3u) & ~3u; }
+
+// pair q of the strict upper triangle of an m x m matrix, row by row
+__device__ inline void tri_pair(int64_t q, int m, int& i, int& j) {
+  const double b = 2.0 * m - 1.0;
+  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
+  auto before = [m](int64_t x) { return x * m - x * (x + 1) / 2; };  // pairs in rows < x
+  if (r < 0) r = 0;
+  if (r > m - 2) r = m - 2;
+  while (r > 0 && before(r) > q) --r;
+  while (r < m - 2 && before(r + 1) <= q) ++r;
+  i = (int)r;
+  j = (int)(q - before(r) + r + 1);
+}
+
+template <int KW>
+__global__ __launch_bounds__(256) void distance_kernel(const int16_t* __restrict__ A, const int16_t* __restrict__ B,
+                                                       const int16_t* __restrict__ recA,
+                                                       const int16_t* __restrict__ recB, int32_t nb, int32_t m_tri,
+                                                       int32_t n, int32_t k, int64_t npairs, int32_t wpb,
+                                                       int32_t* __restrict__ out, int64_t ld) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const uint32_t words = hist_words(k);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(smem) + (size_t)wid * words;
+  const uint16_t* h16 = reinterpret_cast<const uint16_t*>(hist);
+  const int64_t nwaves = (int64_t)gridDim.x * wpb;
+  for (int64_t q = (int64_t)blockIdx.x * wpb + wid; q < npairs; q += nwaves) {
+    int i, j;
+    if (m_tri > 0) {
+      tri_pair(q, m_tri, i, j);
+    } else {
+      i = (int)(q / nb);
+      j = (int)(q - (int64_t)i * nb);
+    }
+    const int16_t* ra = recA + (size_t)i * (k + 2);
+    const int16_t* rb = recB + (size_t)j * (k + 2);
+    const int nea = ra[k], neb = rb[k];
+    int32_t d = -1;
+    if (nea >= 0 && neb >= 0) {
+      for (uint32_t w = (uint32_t)lane; w < words / 4u; w += kWave)
+        reinterpret_cast<uint4*>(hist)[w] = make_uint4(0u, 0u, 0u, 0u);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int16_t* a = A + (size_t)i * n;
+      const int16_t* b = B + (size_t)j * n;
+      for (int v = lane; v < n; v += kWave) {
+        const uint32_t e = (uint32_t)a[v] * (uint32_t)k + (uint32_t)b[v];
+        atomicAdd(&hist[e >> 1], (e & 1u) ? 0x10000u : 1u);  // a count stays below 2^15: no carry
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // class orders in registers: lane holds entries lane, lane + 64, ...
+      int oa[KW], ob[KW];
+#pragma unroll
+      for (int w = 0; w < KW; ++w) {
+        const int t = lane + kWave * w;
+        oa[w] = t < k ? ra[t] : 0;
+        ob[w] = t < k ? rb[t] : 0;
+      }
+      uint32_t takenB = 0u, takenA = 0u;  // bit w: class lane + 64 w already matched
+      uint32_t sab = 0u, sba = 0u;
+      const int steps = nea > neb ? nea : neb;
+      for (int t = 0; t < steps; ++t) {
+        const int tw = t / kWave, tl = t % kWave;
+        int ro = 0, co = 0;
+#pragma unroll
+        for (int w = 0; w < KW; ++w)
+          if (w == tw) {
+            ro = (int)readlane((uint32_t)oa[w], tl);
+            co = (int)readlane((uint32_t)ob[w], tl);
+          }
+        // pass over A: row ro of M, lanes own the columns (classes of B)
+        // pass over B: column co of M, lanes own the rows (classes of A)
+        uint32_t ka = 0u, kb = 0u;
+#pragma unroll
+        for (int w = 0; w < KW; ++w) {
+          const int c = lane + kWave * w;
+          if (c < k) {
+            const uint32_t va = (t < nea && !((takenB >> w) & 1u)) ? (uint32_t)h16[ro * k + c] : 0u;
+            const uint32_t vb = (t < neb && !((takenA >> w) & 1u)) ? (uint32_t)h16[c * k + co] : 0u;
+            ka = max(ka, va ? (va << 16) | (0xffffu - (uint32_t)c) : 0u);
+            kb = max(kb, vb ? (vb << 16) | (0xffffu - (uint32_t)c) : 0u);
+          }
+        }
+        const uint32_t ma = wave_max_u32(ka), mb = wave_max_u32(kb);
+        if (ma) {
+          sab += ma >> 16;
+          const int c = 0xffff - (int)(ma & 0xffffu);
+          if ((c & (kWave - 1)) == lane) takenB |= 1u << (c / kWave);
+        }
+        if (mb) {
+          sba += mb >> 16;
+          const int c = 0xffff - (int)(mb & 0xffffu);
+          if ((c & (kWave - 1)) == lane) takenA |= 1u << (c / kWave);
+        }
+      }
+      d = n - (int32_t)(sab > sba ? sab : sba);
+    }
+    if (lane == 0) {
+      out[(size_t)i * ld + j] = d;
+      if (m_tri > 0) out[(size_t)j * ld + i] = d;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void diag_zero_kernel(int32_t m, int32_t* __restrict__ out, int64_t ld) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[(size_t)i * ld + i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// population update: the pool's quality order (f ascending, index ascending)
+// by counting, then one workgroup takes it greedily
+__global__ __launch_bounds__(256) void pool_rank_kernel(const int32_t* __restrict__ fa, int32_t na,
+                                                        const int32_t* __restrict__ fb, int32_t nb,
+                                                        int32_t* __restrict__ order) {
+  __shared__ uint64_t tile[1024];
+  const int total = na + nb;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  auto key = [&](int x) {
+    const int32_t f = x < na ? fa[x] : fb[x - na];
+    return ((uint64_t)((uint32_t)f ^ 0x80000000u) << 32) | (uint32_t)x;  // signed order of f, then index
+  };
+  const uint64_t mine = i < total ? key(i) : ~0ull;
+  uint32_t rank = 0u;
+  for (int base = 0; base < total; base += 1024) {
+    const int cnt = min(1024, total - base);
+    __syncthreads();
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) tile[x] = key(base + x);
+    __syncthreads();
+    for (int x = 0; x < cnt; ++x) rank += tile[x] < mine;
+  }
+  if (i < total) order[rank] = i;
+}
+
+constexpr int kMaxPool = 1 << 16;
+
+__global__ __launch_bounds__(1024) void spacing_kernel(const int32_t* __restrict__ order, int32_t total, int32_t keep,
+                                                       const int32_t* __restrict__ dist, int64_t ld,
+                                                       int32_t spacing, int32_t* __restrict__ pick,
+                                                       int32_t* __restrict__ n_spaced) {
+  __shared__ uint32_t taken[kMaxPool / 32];
+  const int tid = threadIdx.x;
+  for (int w = tid; w < (total + 31) / 32; w += blockDim.x) taken[w] = 0u;
+  __syncthreads();
+  int count = 0;  // the same in every thread
+  for (int r = 0; r < total && count < keep; ++r) {
+    const int c = order[r];
+    int ok = 1;
+    for (int s = tid; s < count; s += blockDim.x) {
+      const int o = pick[s];
+      const int lo = c < o ? c : o, hi = c < o ? o : c;
+      ok &= dist[(size_t)lo * ld + hi] > spacing;  // the upper triangle holds the pool's distances
+    }
+    if (__syncthreads_and(ok)) {
+      if (tid == 0) {
+        pick[count] = c;
+        taken[c / 32] |= 1u << (c % 32);
+      }
+      ++count;
+      __syncthreads();  // pick[count - 1] is read by every thread from the next candidate on
+    }
+  }
+  if (tid == 0) {
+    *n_spaced = count;
+    for (int r = 0; r < total && count < keep; ++r) {
+      const int c = order[r];
+      if (!((taken[c / 32] >> (c % 32)) & 1u)) pick[count++] = c;
+    }
+  }
+}
+
+// out[a][b] = dist[min(pa, pb)][max(pa, pb)] for a != b, 0 on the diagonal
+__global__ __launch_bounds__(256) void gather_dist_kernel(const int32_t* __restrict__ dist, int64_t ld,
+                                                          const int32_t* __restrict__ idx, int32_t count,
+                                                          int32_t* __restrict__ out, int64_t ld_out) {
+  const int a = blockIdx.x;
+  const int pa = idx[a];
+  for (int b = threadIdx.x; b < count; b += blockDim.x) {
+    const int pb = idx[b];
+    const int lo = pa < pb ? pa : pb, hi = pa < pb ? pb : pa;
+    out[(size_t)a * ld_out + b] = a == b ? 0 : dist[(size_t)lo * ld + hi];
+  }
+}
+
+// row r of out = pool member pick[r] (a row of ra for indices below na, else
+// of rb); an index outside the pool gives a row of -1 and score -1
+__global__ __launch_bounds__(256) void gather_pool_kernel(const int16_t* __restrict__ ra, const int32_t* __restrict__ fa,
+                                                          int32_t na, const int16_t* __restrict__ rb,
+                                                          const int32_t* __restrict__ fb, int32_t nb, int32_t n,
+                                                          const int32_t* __restrict__ pick, int16_t* __restrict__ out,
+                                                          int32_t* __restrict__ fout) {
+  const int64_t r = blockIdx.x;
+  const int s = pick[r];
+  const bool ok = s >= 0 && s < na + nb;
+  const int16_t* src = !ok ? nullptr : (s < na ? ra + (size_t)s * n : rb + (size_t)(s - na) * n);
+  for (int v = threadIdx.x; v < n; v += blockDim.x) out[(size_t)r * n + v] = ok ? src[v] : (int16_t)-1;
+  if (threadIdx.x == 0) fout[r] = !ok ? -1 : (s < na ? fa[s] : fb[s - na]);
+}
+
+// K nearest of row i: K extractions of the smallest key dist << 16 | j
+// above the last one taken (keys are distinct: j is part of them)
+__global__ __launch_bounds__(256) void nearest_kernel(const int32_t* __restrict__ dist, int64_t ld, int32_t p,
+                                                      int32_t K, int32_t* __restrict__ nn) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= p) return;  // whole waves leave together
+  const int32_t* row = dist + (size_t)i * ld;
+  uint32_t last = 0u;
+  bool first = true;
+  for (int t = 0; t < K; ++t) {
+    uint32_t best = 0xffffffffu;
+    for (int j = lane; j < p; j += kWave) {
+      const uint32_t key = ((uint32_t)row[j] << 16) | (uint32_t)j;
+      if (j != i && (first || key > last)) best = min(best, key);
+    }
+    last = wave_min_u32(best);
+    first = false;
+    if (lane == 0) nn[(size_t)i * K + t] = (int32_t)(last & 0xffffu);
+  }
+}
+
+}  // namespace dlm
+
+using namespace dlm;
+
+extern "C" {
+
+int dlm_partition_distance(int32_t n, int32_t k, const int16_t* a, int32_t na, const int16_t* b, int32_t nb,
+                           int32_t tri, int32_t* out, int64_t ld, void* workspace, void* stream) {
+  if (n < 1 || n > 32767 || k < 1 || k > kMaxDistK || na < 0 || nb < 0 || (tri != 0 && tri != 1))
+    return set_error(DLM_E_INVAL, "dlm_partition_distance: n=%d k=%d na=%d nb=%d tri=%d", n, k, na, nb, tri);
+  if (tri && (a != b || na != nb))
+    return set_error(DLM_E_INVAL, "dlm_partition_distance: tri needs the same rows on both sides");
+  if (ld < nb) return set_error(DLM_E_INVAL, "dlm_partition_distance: ld=%lld < nb=%d", (long long)ld, nb);
+  if (na == 0 || nb == 0) return DLM_OK;
+  if (!a || !b || !out || !workspace) return set_error(DLM_E_INVAL, "dlm_partition_distance: null buffer");
+  hipStream_t s = (hipStream_t)stream;
+  int16_t* recA = (int16_t*)workspace;
+  int16_t* recB = tri ? recA : recA + (size_t)na * (k + 2);
+  hipLaunchKernelGGL(class_order_kernel, dim3(na), dim3(kWave), 0, s, a, n, k, recA);
+  DLM_HIP(hipGetLastError());
+  if (!tri) {
+    hipLaunchKernelGGL(class_order_kernel, dim3(nb), dim3(kWave), 0, s, b, n, k, recB);
+    DLM_HIP(hipGetLastError());
+  }
+  const int64_t npairs = tri ? (int64_t)na * (na - 1) / 2 : (int64_t)na * nb;
+  if (tri) {
+    hipLaunchKernelGGL(diag_zero_kernel, dim3((na + 255) / 256), dim3(256), 0, s, na, out, ld);
+    DLM_HIP(hipGetLastError());
+  }
+  if (npairs == 0) return DLM_OK;
+  const uint32_t wave_bytes = 4u * hist_words(k);
+  int wpb = (int)(65536u / wave_bytes);  // up to 4 waves and 64 KB of LDS per workgroup
+  wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+  const size_t lds = (size_t)wpb * wave_bytes;
+  const int64_t blocks_needed = (npairs + wpb - 1) / wpb;
+  const int64_t cap = (int64_t)device_cu_count() * 64;
+  const unsigned grid = (unsigned)(blocks_needed < cap ? blocks_needed : cap);
+  const int kw = (k + kWave - 1) / kWave;
+  auto launch = [&](auto kern) -> int {
+    DLM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWave * wpb), lds, s, a, b, recA, recB, nb, tri ? na : 0, n, k,
+                       npairs, wpb, out, ld);
+    DLM_HIP(hipGetLastError());
+    return DLM_OK;
+  };
+  switch (kw) {
+    case 1: return launch(distance_kernel<1>);
+    case 2: return launch(distance_kernel<2>);
+    case 3: return launch(distance_kernel<3>);
+    default: return launch(distance_kernel<4>);
+  }
+}
+
+int dlm_spacing_update(const int32_t* fa, int32_t na, const int32_t* fb, int32_t nb, const int32_t* dist, int64_t ld,
+                       int32_t keep, int32_t spacing, int32_t* pick, int32_t* n_spaced, void* workspace,
+                       void* stream) {
+  const int64_t total = (int64_t)na + nb;
+  if (na < 0 || nb < 0 || total > kMaxPool || keep < 0 || keep > total || ld < total)
+    return set_error(DLM_E_INVAL, "dlm_spacing_update: na=%d nb=%d keep=%d ld=%lld", na, nb, keep, (long long)ld);
+  if (!pick || !n_spaced || (total > 0 && (!dist || !workspace)) || (na > 0 && !fa) || (nb > 0 && !fb))
+    return set_error(DLM_E_INVAL, "dlm_spacing_update: null buffer");
+  hipStream_t s = (hipStream_t)stream;
+  int32_t* order = (int32_t*)workspace;
+  if (total > 0) {
+    hipLaunchKernelGGL(pool_rank_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, fa, na, fb, nb,
+                       order);
+    DLM_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(spacing_kernel, dim3(1), dim3(1024), 0, s, order, (int32_t)total, keep, dist, ld, spacing, pick,
+                     n_spaced);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_gather_distances(const int32_t* dist, int64_t ld, const int32_t* idx, int32_t count, int32_t* out,
+                         int64_t ld_out, void* stream) {
+  if (count < 0 || ld_out < count) return set_error(DLM_E_INVAL, "dlm_gather_distances: count=%d", count);
+  if (count == 0) return DLM_OK;
+  if (!dist || !idx || !out) return set_error(DLM_E_INVAL, "dlm_gather_distances: null buffer");
+  hipLaunchKernelGGL(gather_dist_kernel, dim3(count), dim3(256), 0, (hipStream_t)stream, dist, ld, idx, count, out,
+                     ld_out);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_gather_pool(const int16_t* ra, const int32_t* fa, int32_t na, const int16_t* rb, const int32_t* fb,
+                    int32_t nb, int32_t n, const int32_t* pick, int32_t count, int16_t* out, int32_t* fout,
+                    void* stream) {
+  if (na < 0 || nb < 0 || n < 1 || count < 0)
+    return set_error(DLM_E_INVAL, "dlm_gather_pool: na=%d nb=%d n=%d count=%d", na, nb, n, count);
+  if (count == 0) return DLM_OK;
+  if (!pick || !out || !fout || (na > 0 && (!ra || !fa)) || (nb > 0 && (!rb || !fb)))
+    return set_error(DLM_E_INVAL, "dlm_gather_pool: null buffer");
+  hipLaunchKernelGGL(gather_pool_kernel, dim3(count), dim3(256), 0, (hipStream_t)stream, ra, fa, na, rb, fb, nb, n,
+                     pick, out, fout);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_nearest(const int32_t* dist, int64_t ld, int32_t p, int32_t K, int32_t* nn, void* stream) {
+  if (p < 0 || p > kMaxPool || K < 0 || (p > 0 && K > p - 1) || ld < p)
+    return set_error(DLM_E_INVAL, "dlm_nearest: p=%d K=%d ld=%lld", p, K, (long long)ld);
+  if (p == 0 || K == 0) return DLM_OK;
+  if (!dist || !nn) return set_error(DLM_E_INVAL, "dlm_nearest: null buffer");
+  hipLaunchKernelGGL(nearest_kernel, dim3((p + 3) / 4), dim3(256), 0, (hipStream_t)stream, dist, ld, p, K, nn);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+}  // extern "C"

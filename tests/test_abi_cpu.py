@@ -72,3 +72,29 @@ def test_null_arguments(L):
     assert L.dlm_graph_info(None, None, None, None) == -1
     assert L.dlm_evaluate(None, 2, None, 1, None, None, None) == -1
     assert L.dlm_init_population(None, 2, 1, 0, 0, 0, None, None, None) == -1
+
+
+def test_diversity_argument_checks(L):
+    """Bad sizes and null buffers are rejected before any device work."""
+    fake = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    # k outside [1, 256], n outside [1, 32767]
+    assert L.dlm_partition_distance(10, 0, fake, 1, fake, 1, 0, fake, 1, fake, None) == -1
+    assert L.dlm_partition_distance(10, 257, fake, 1, fake, 1, 0, fake, 1, fake, None) == -1
+    assert L.dlm_partition_distance(0, 3, fake, 1, fake, 1, 0, fake, 1, fake, None) == -1
+    # the triangle form needs the same rows on both sides; ld below the row length
+    assert L.dlm_partition_distance(10, 3, fake, 2, C.c_void_p(32), 2, 1, fake, 2, fake, None) == -1
+    assert L.dlm_partition_distance(10, 3, fake, 2, fake, 3, 0, fake, 2, fake, None) == -1
+    assert L.dlm_partition_distance(10, 3, None, 2, fake, 2, 0, fake, 2, fake, None) == -1
+    # keep above the pool, ld below the pool, pool above 65536
+    assert L.dlm_spacing_update(fake, 2, fake, 2, fake, 4, 5, 0, fake, fake, fake, None) == -1
+    assert L.dlm_spacing_update(fake, 2, fake, 2, fake, 3, 2, 0, fake, fake, fake, None) == -1
+    assert L.dlm_spacing_update(fake, 40000, fake, 40000, fake, 80000, 2, 0, fake, fake, fake, None) == -1
+    assert L.dlm_spacing_update(fake, 2, fake, 2, fake, 4, 2, 0, None, fake, fake, None) == -1
+    # K must stay below p
+    assert L.dlm_nearest(fake, 4, 4, 4, fake, None) == -1
+    assert L.dlm_nearest(fake, 3, 4, 2, fake, None) == -1
+    assert L.dlm_gather_pool(fake, fake, -1, fake, fake, 1, 5, fake, 1, fake, fake, None) == -1
+    assert L.dlm_gather_distances(fake, 4, fake, 5, fake, 4, None) == -1
+    # empty requests are no-ops
+    assert L.dlm_partition_distance(10, 3, None, 0, None, 0, 0, None, 0, None, None) == 0
+    assert L.dlm_nearest(None, 1, 0, 0, None, None) == 0
