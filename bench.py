@@ -136,6 +136,9 @@ def main():
     ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
     ap.add_argument("--k", type=int, default=0, help="memetic1000: colours (default: the workload's 85)")
     ap.add_argument("--seeds", default="1", help="memetic1000: comma-separated loop seeds")
+    ap.add_argument("--diversity", type=int, default=0,
+                    help="memetic1000: K > 0 runs the loops with the paper's diversity steps (K nearest "
+                         "neighbours, one child per individual, spacing update)")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
@@ -349,7 +352,8 @@ def bench_memetic(args, w, dlm, torch):
             r = memetic.run(G, k, pop, T, learned=(name == "learned"), seed=sd,
                             cutoff_s=args.cutoff, children_per_pair=e["children_per_pair"],
                             keep_frac=e["keep_frac"], scorer_params=scorer_weights(g.n, seed=0),
-                            batch=e["batch"], epochs=e["epochs"], lr=e["lr"], log=log)
+                            batch=e["batch"], epochs=e["epochs"], lr=e["lr"], log=log,
+                            diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
             runs.append({"seed": sd, "time_to_legal_s": r.time_to_legal, "best_f": r.best,
                          "generations": r.generations, "wall_s": r.wall,
                          "tabu_moves_per_s": r.tabu_moves / r.wall,
@@ -366,7 +370,7 @@ def bench_memetic(args, w, dlm, torch):
            "config": {"workload": "memetic1000", "graph": "G(n=1000, p=0.5) seed 0", "k": k,
                       "population": pop, "children_per_pair": e["children_per_pair"],
                       "keep_frac": e["keep_frac"], "iters_per_tabu": T, "cutoff_s": args.cutoff,
-                      "seeds": seeds},
+                      "seeds": seeds, "diversity_neighbours": args.diversity},
            "loops": res}
     print(json.dumps(out), flush=True)
 

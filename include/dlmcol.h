@@ -327,6 +327,14 @@ int dlm_standardize(const int32_t* f_dev, int32_t count, float* out_dev, void* s
  * Philox(seed; i, gen, 0, 0x80000009). */
 int dlm_random_pairs(int32_t pop, uint64_t seed, uint32_t gen, int32_t* pairs_dev, void* stream);
 
+/* One offspring per individual (eq. select_cross with K-nearest matching,
+ * Section 2.6): idx_dev[g] = gK + j for the child j < K of group g (children
+ * gK .. gK + K - 1) with the smallest FP32 score, ties by smaller j
+ * (DLM_SELECT_TOP), or j = floor(w0 K / 2^32), w0 = word 0 of
+ * Philox(seed; g, gen, 0, 0x8000000A) (DLM_SELECT_RANDOM, scores unused). */
+int dlm_select_groups(const float* scores_dev, int32_t groups, int32_t K, int32_t mode, uint64_t seed,
+                      uint32_t gen, int32_t* idx_dev, void* stream);
+
 /* Keep the pop best of parents (indices 0..pop-1) and offspring (indices
  * pop..2pop-1) by score ascending, ties by index: out_dev int16[pop][n] and
  * f_out_dev int32[pop] in rank order.  workspace_dev: 24 * pop bytes. */

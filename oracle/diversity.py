@@ -30,11 +30,18 @@ Three steps of a memetic generation (Sections 2.4 to 2.6 of the paper):
   population is full (the paper does not say what happens then), the best
   of the individuals left out fill the remaining places.
 * K-nearest-neighbour parent matching (Section 2.6): the K individuals
-  closest to each one (ties by index), itself excluded.
+  closest to each one (ties by index), itself excluded; each individual's K
+  GPX children (one per neighbour) then yield one offspring: the child with
+  the smallest predicted score (eq. select_cross), or for the plain loop a
+  uniformly drawn one.
 """
 from __future__ import annotations
 
 import numpy as np
+
+from . import philox, uniform
+
+D_SELGROUP = 0x8000000A  # Philox domain of the plain loop's draw within a group
 
 
 def overlap(a: np.ndarray, b: np.ndarray, k: int) -> np.ndarray:
@@ -117,4 +124,24 @@ def nearest(dist: np.ndarray, K: int) -> np.ndarray:
     for i in range(p):
         cand = sorted((int(dist[i][j]), j) for j in range(p) if j != i)
         out[i] = [j for _, j in cand[:K]]
+    return out
+
+
+def select_groups(scores: np.ndarray | None, groups: int, K: int, mode: str, seed: int = 0,
+                  gen: int = 0) -> np.ndarray:
+    """One child per group of K consecutive children (group g = children
+    gK .. gK + K - 1).  "top": the smallest FP32 score, ties by smaller
+    index.  "random": child gK + floor(w0 K / 2^32), w0 = word 0 of
+    Philox(seed; g, gen, 0, D_SELGROUP)."""
+    out = np.zeros(groups, dtype=np.int32)
+    for g in range(groups):
+        if mode == "top":
+            s = np.asarray(scores[g * K:(g + 1) * K], dtype=np.float32)
+            best = 0
+            for j in range(1, K):
+                if s[j] < s[best]:
+                    best = j
+            out[g] = g * K + best
+        else:
+            out[g] = g * K + uniform(philox(g, gen, 0, D_SELGROUP, seed)[0], K)
     return out

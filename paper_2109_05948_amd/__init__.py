@@ -24,6 +24,7 @@ from ._abi import (  # noqa: F401
     standardize,
     gpx_batch,
     select,
+    select_groups,
     init_population,
     lib,
     tabu_batch,

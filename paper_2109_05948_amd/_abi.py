@@ -34,7 +34,7 @@ EXPORTS = [
     "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
     "dlm_multi_plan_destroy", "dlm_multi_autotune", "dlm_probe_lds_bandwidth",
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
-    "dlm_nearest",
+    "dlm_nearest", "dlm_select_groups",
 ]
 
 
@@ -94,6 +94,7 @@ def lib():
             L.dlm_gather_distances.argtypes = [P, I64, P, I32, P, I64, P]
             L.dlm_gather_pool.argtypes = [P, P, I32, P, P, I32, I32, P, I32, P, P, P]
             L.dlm_nearest.argtypes = [P, I64, I32, I32, P, P]
+            L.dlm_select_groups.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -475,6 +476,21 @@ def gather_pool(ra: torch.Tensor, fa: torch.Tensor, rb: torch.Tensor, fb: torch.
         _ptr(ra), _ptr(fa), ra.shape[0], _ptr(rb), _ptr(fb), rb.shape[0], n, _ptr(pick), pick.shape[0],
         _ptr(out), _ptr(fout), _stream(stream)))
     return out, fout
+
+
+def select_groups(scores: torch.Tensor | None, groups: int, K: int, mode: str = "top", seed: int = 0,
+                  gen: int = 0, stream=None):
+    """dlm_select_groups -> int32 [groups]: one child index per group of K."""
+    m = {"top": 0, "random": 1}[mode]
+    if m == 0:
+        _dev(scores, torch.float32, "scores")
+        if scores.shape[0] < groups * K:
+            raise ValueError("scores shorter than groups * K")
+    out = torch.empty(groups, dtype=torch.int32, device="cuda")
+    _check("dlm_select_groups", lib().dlm_select_groups(_ptr(scores) if m == 0 else None, groups, K, m,
+                                                        seed & (2**64 - 1), gen & 0xffffffff, _ptr(out),
+                                                        _stream(stream)))
+    return out
 
 
 def nearest(dist: torch.Tensor, K: int, p: int | None = None, stream=None):

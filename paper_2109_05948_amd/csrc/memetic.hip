@@ -6,6 +6,7 @@
 namespace dlm {
 
 constexpr uint32_t kDomPair = 0x80000009u;
+constexpr uint32_t kDomSelGroup = 0x8000000Au;
 
 __global__ __launch_bounds__(256) void gather_rows_kernel(const int16_t* __restrict__ src, int32_t rows,
                                                           int32_t n, const int32_t* __restrict__ idx,
@@ -103,6 +104,30 @@ __global__ __launch_bounds__(256) void merge_copy_kernel(const int16_t* __restri
   if (threadIdx.x == 0) fout[r] = s < pop ? fpar[s] : foff[s - pop];
 }
 
+// one child per group of K consecutive children: the smallest score (ties
+// by index) or a Philox draw
+__global__ __launch_bounds__(256) void select_groups_kernel(const float* __restrict__ scores, int32_t groups,
+                                                            int32_t K, int32_t mode, Key key, uint32_t gen,
+                                                            int32_t* __restrict__ idx) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= groups) return;
+  int best = 0;
+  if (mode == DLM_SELECT_TOP) {
+    const float* s = scores + (size_t)g * K;
+    float bs = s[0];
+    for (int j = 1; j < K; ++j) {
+      const float x = s[j];
+      if (x < bs) {
+        bs = x;
+        best = j;
+      }
+    }
+  } else {
+    best = (int)lemire(philox_w0((uint32_t)g, gen, 0u, kDomSelGroup, key), (uint32_t)K);
+  }
+  idx[g] = g * K + best;
+}
+
 }  // namespace dlm
 
 using namespace dlm;
@@ -131,6 +156,19 @@ int dlm_random_pairs(int32_t pop, uint64_t seed, uint32_t gen, int32_t* pairs, v
   if (pop == 0) return DLM_OK;
   hipLaunchKernelGGL(random_pairs_kernel, dim3((pop + 255) / 256), dim3(256), 0, (hipStream_t)stream, pop,
                      make_key(seed), gen, pairs);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_select_groups(const float* scores, int32_t groups, int32_t K, int32_t mode, uint64_t seed, uint32_t gen,
+                      int32_t* idx, void* stream) {
+  if (groups < 0 || K < 1 || (mode != DLM_SELECT_TOP && mode != DLM_SELECT_RANDOM) ||
+      (int64_t)groups * K > 0x7fffffffll)
+    return set_error(DLM_E_INVAL, "dlm_select_groups: groups=%d K=%d mode=%d", groups, K, mode);
+  if (groups == 0) return DLM_OK;
+  if (!idx || (mode == DLM_SELECT_TOP && !scores)) return set_error(DLM_E_INVAL, "dlm_select_groups: null buffer");
+  hipLaunchKernelGGL(select_groups_kernel, dim3((groups + 255) / 256), dim3(256), 0, (hipStream_t)stream, scores,
+                     groups, K, mode, make_key(seed), gen, idx);
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }

@@ -75,3 +75,63 @@ def test_short_memetic_loop(dlm, dev, learned):
     assert res.tabu_moves > 0
     if learned and res.generations:
         assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()
+
+
+def test_select_groups(dlm, dev):
+    from oracle import diversity as dv
+    rng = np.random.default_rng(3)
+    for groups, K in ((1, 1), (7, 3), (500, 16)):
+        s = rng.integers(0, 6, groups * K).astype(np.float32) * 0.25  # many ties
+        say(f"select_groups {groups}x{K}")
+        got = dlm.select_groups(torch.from_numpy(s).cuda(), groups, K, "top").cpu().numpy()
+        assert (got == dv.select_groups(s, groups, K, "top")).all()
+        got = dlm.select_groups(None, groups, K, "random", seed=21, gen=5).cpu().numpy()
+        assert (got == dv.select_groups(None, groups, K, "random", seed=21, gen=5)).all()
+
+
+def test_diversity_generation_replay(dlm, dev):
+    """One generation of the loop with the diversity steps (plain selection),
+    replayed step by step with the oracle: initial search, distances,
+    nearest neighbours, GPX, group draw, search of the offspring, pool
+    distances, spacing update.  The resulting population must be identical."""
+    from oracle import diversity as dv
+    from paper_2109_05948_amd import memetic
+    g = gnp(100, 0.5, seed=5)
+    k, pop, T, K, seed = 11, 24, 500, 5, 3
+    G = dlm.Graph.from_csr(g)
+    say("memetic diversity replay")
+    res = memetic.run(G, k, pop, T, learned=False, seed=seed, cutoff_s=60, max_generations=1,
+                      diversity=True, neighbours=K)
+    assert res.generations == 1
+    r0 = oracle.tabucol_batch(g, oracle.init_random(g.n, k, pop, seed=seed), np.arange(pop), k, T,
+                              seed ^ memetic.SEED_TABU)
+    cols, f = r0["colors"], r0["f_best"]
+    nn = dv.nearest(dv.distance_matrix(cols, cols, k), K)
+    pairs = np.stack([np.repeat(np.arange(pop), K), nn.reshape(-1)], 1).astype(np.int32)
+    children = oracle.gpx_batch(k, cols, pairs, 1, pop * K, seed ^ memetic.SEED_GPX)
+    off = children[dv.select_groups(None, pop, K, "random", seed=seed ^ memetic.SEED_SEL, gen=1)]
+    r1 = oracle.tabucol_batch(g, off, np.arange(pop, 2 * pop), k, T, seed ^ memetic.SEED_TABU)
+    rows = np.concatenate([cols, r1["colors"]])
+    fs = np.concatenate([f, r1["f_best"]])
+    pick, _ = dv.spacing_update(fs, dv.distance_matrix(rows, rows, k), pop, g.n // 10)
+    assert (res.colors.cpu().numpy() == rows[pick]).all()
+    assert (res.f.cpu().numpy() == fs[pick]).all()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_short_memetic_loop_diversity(dlm, dev, learned):
+    from paper_2109_05948_amd import memetic
+    g = gnp(120, 0.5, seed=3)
+    k, pop = 16, 64
+    G = dlm.Graph.from_csr(g)
+    say(f"memetic diversity learned={learned}")
+    res = memetic.run(G, k, pop, 600, learned=learned, seed=1, cutoff_s=60, max_generations=4,
+                      scorer_params=scorer_weights(g.n, seed=0), batch=64, epochs=2, diversity=True,
+                      neighbours=8)
+    bests = [h[2] for h in res.history]
+    assert all(b2 <= b1 for b1, b2 in zip(bests, bests[1:]))  # the spacing update takes the best first
+    assert res.best == bests[-1] == int(res.f.min().item())
+    conf, _ = dlm.evaluate(G, res.colors, k)
+    assert (conf == res.f).all()
+    if learned and res.generations:
+        assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()

@@ -148,3 +148,24 @@ def test_nearest_hand_case():
                   [2, 7, 5, 0]])
     assert dv.nearest(d, 2).tolist() == [[2, 3], [2, 0], [1, 0], [0, 2]]
     assert dv.nearest(d, 3).tolist() == [[2, 3, 1], [2, 0, 3], [1, 0, 3], [0, 2, 1]]
+
+
+def test_select_groups_top_hand_case():
+    s = np.array([3.0, 1.0, 1.0, 2.0, 0.5, -1.0, 7.0, -1.0], np.float32)
+    assert dv.select_groups(s, 2, 4, "top").tolist() == [1, 5]
+    assert dv.select_groups(s, 4, 2, "top").tolist() == [1, 2, 5, 7]
+    assert dv.select_groups(s, 8, 1, "top").tolist() == list(range(8))
+
+
+def test_select_groups_random_is_uniform_and_seeded():
+    import oracle
+    K, groups = 5, 4000
+    a = dv.select_groups(None, groups, K, "random", seed=9, gen=3)
+    assert ((a // K) == np.arange(groups)).all()
+    counts = np.bincount(a % K, minlength=K)
+    assert counts.min() > 0.8 * groups / K  # each position drawn about equally often
+    b = dv.select_groups(None, groups, K, "random", seed=9, gen=4)
+    assert (a != b).any()
+    # the draw is word 0 of the published Philox4x32-10 scaled to [0, K)
+    w0 = oracle.philox(17, 3, 0, dv.D_SELGROUP, 9)[0]
+    assert a[17] == 17 * K + (w0 * K >> 32)
