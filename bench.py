@@ -48,11 +48,17 @@ KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd
                   "paper_2109_05948_amd/csrc/dlm_common.h")
 
 
-def kernel_sources_digest() -> str:
+# HBM bytes of the two distance launches of one diversity step (old x new
+# block + new x new triangle), from the same counter runs
+DIVERSITY_TRAFFIC = {"sources_sha256": "2720dafe284167f0c2286762c400aea2378c95d8d40f8127eadf50ec5ebafe82", "bytes": 1747147199}  # profiles/distance_diversity_gnp500.md
+DIVERSITY_SOURCES = ("paper_2109_05948_amd/csrc/diversity.hip", "paper_2109_05948_amd/csrc/dlm_common.h")
+
+
+def kernel_sources_digest(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(root, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -464,7 +470,7 @@ def bench_diversity(args, w, dlm, torch):
         if ev:
             ev[0].record(stream)
         dlm.partition_distance(old, k, new, out=pool[:p, p:])
-        dlm.partition_distance(new, k, out=pool[p:, p:])
+        dlm.partition_distance(new, k, out=pool[p:, p:], upper_only=True)
         if ev:
             ev[1].record(stream)
         pick, nsp = dlm.spacing_update(f_old, f_new, pool, p, spacing)
@@ -503,7 +509,10 @@ def bench_diversity(args, w, dlm, torch):
            "distance_ms": dist_ms, "spacing_update_ms": upd_ms, "gather_nearest_ms": rest_ms,
            "n_spaced": int(nsp.item()),
            "roofline": {"bound": "alu", "achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                        "frac": tops / ALU_PEAK_TOPS, "traffic": None, "kernel": "distance_kernel",
+                        "frac": tops / ALU_PEAK_TOPS, "kernel": "distance_kernel",
+                        "traffic": (DIVERSITY_TRAFFIC["bytes"] if p == 8192 and
+                                    kernel_sources_digest(DIVERSITY_SOURCES) == DIVERSITY_TRAFFIC["sources_sha256"]
+                                    else None),
                         "ops_per_pair": n + 2 * k * k}}
     print(json.dumps(out), flush=True)
 

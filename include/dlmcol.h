@@ -365,7 +365,9 @@ int dlm_pop_update(const int16_t* parents_dev, const int32_t* f_parents_dev,
  *   a_dev, b_dev  int16 device colourings [na][n], [nb][n], colours in [0, k);
  *                 a pair with a colour outside [0, k) gets -1
  *   tri           0: all na x nb pairs; 1: a_dev == b_dev and na == nb, the
- *                 pairs i < j, mirrored below the diagonal, diagonal 0
+ *                 pairs i < j, mirrored below the diagonal, diagonal 0;
+ *                 2: as 1 without the mirror (the strict lower triangle is
+ *                 not written), the form a pool matrix needs
  *   out_dev       int32, row stride ld >= nb elements
  *   workspace_dev caller-owned scratch of 2 (k + 2) (na + nb) bytes (the
  *                 class orders)

@@ -409,10 +409,11 @@ def pop_update(parents: torch.Tensor, f_parents: torch.Tensor, offspring: torch.
 
 
 def partition_distance(a: torch.Tensor, k: int, b: torch.Tensor | None = None, out: torch.Tensor | None = None,
-                       stream=None):
+                       upper_only: bool = False, stream=None):
     """dlm_partition_distance -> int32 [len(a), len(b)]; b None: the
-    triangle form over the rows of a (symmetric, zero diagonal).  ``out`` may
-    be a row-strided view (e.g. a block of a pool matrix)."""
+    triangle form over the rows of a (symmetric, zero diagonal; with
+    upper_only the strict lower triangle is left as it was).  ``out`` may be
+    a row-strided view (e.g. a block of a pool matrix)."""
     _dev(a, torch.int16, "a")
     tri = b is None
     b = a if tri else b
@@ -426,7 +427,8 @@ def partition_distance(a: torch.Tensor, k: int, b: torch.Tensor | None = None, o
         raise ValueError(f"out must be int32 [{na}, {nb}] with unit column stride")
     ws = torch.empty(((k + 2) * (na + nb) + 1) // 2 + 1, dtype=torch.int32, device=a.device)
     _check("dlm_partition_distance", lib().dlm_partition_distance(
-        n, k, _ptr(a), na, _ptr(b), nb, 1 if tri else 0, _ptr(out), out.stride(0), _ptr(ws), _stream(stream)))
+        n, k, _ptr(a), na, _ptr(b), nb, (2 if upper_only else 1) if tri else 0, _ptr(out), out.stride(0), _ptr(ws),
+        _stream(stream)))
     return out
 
 

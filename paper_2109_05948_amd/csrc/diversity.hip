@@ -62,21 +62,31 @@ __global__ __launch_bounds__(64) void class_order_kernel(const int16_t* __restri
   }
 }
 
+// wave maxima of two values at once: four in-row DPP steps, then
+// row_bcast:15 and row_bcast:31 carry the row maxima up to lane 63 (one
+// readlane instead of four).  The two chains alternate, so each one's DPP
+// steps fill the other's wait states.
+__device__ __forceinline__ void wave_max2(uint32_t& a, uint32_t& b) {
+  a = max(a, dpp_mov<dpp::kXor1>(a));
+  b = max(b, dpp_mov<dpp::kXor1>(b));
+  a = max(a, dpp_mov<dpp::kXor2>(a));
+  b = max(b, dpp_mov<dpp::kXor2>(b));
+  a = max(a, dpp_mov<dpp::kHalfMirror>(a));
+  b = max(b, dpp_mov<dpp::kHalfMirror>(b));
+  a = max(a, dpp_mov<dpp::kMirror>(a));
+  b = max(b, dpp_mov<dpp::kMirror>(b));
+  // rows 1 and 3 take lane 15 of the row below, then rows 2 and 3 take lane
+  // 31; lanes outside the row mask keep the old operand, 0, which max ignores
+  a = max(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x142, 0xa, 0xf, false));
+  b = max(b, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)b, 0x142, 0xa, 0xf, false));
+  a = max(a, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a, 0x143, 0xc, 0xf, false));
+  b = max(b, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)b, 0x143, 0xc, 0xf, false));
+  a = readlane(a, 63);
+  b = readlane(b, 63);
+}
+
 // words of one wave's overlap table, a multiple of 4 (cleared with 16-byte stores)
 __host__ __device__ inline uint32_t hist_words(int k) { return (((uint32_t)(k * k) + 1u) / 2u + 3u) & ~3u; }
-
-// pair q of the strict upper triangle of an m x m matrix, row by row
-__device__ inline void tri_pair(int64_t q, int m, int& i, int& j) {
-  const double b = 2.0 * m - 1.0;
-  int64_t r = (int64_t)((b - sqrt(b * b - 8.0 * (double)q)) * 0.5);
-  auto before = [m](int64_t x) { return x * m - x * (x + 1) / 2; };  // pairs in rows < x
-  if (r < 0) r = 0;
-  if (r > m - 2) r = m - 2;
-  while (r > 0 && before(r) > q) --r;
-  while (r < m - 2 && before(r + 1) <= q) ++r;
-  i = (int)r;
-  j = (int)(q - before(r) + r + 1);
-}
 
 template <int KW>
 __global__ __launch_bounds__(256) void distance_kernel(const int16_t* __restrict__ A, const int16_t* __restrict__ B,
@@ -91,13 +101,13 @@ __global__ __launch_bounds__(256) void distance_kernel(const int16_t* __restrict
   const uint16_t* h16 = reinterpret_cast<const uint16_t*>(hist);
   const int64_t nwaves = (int64_t)gridDim.x * wpb;
   for (int64_t q = (int64_t)blockIdx.x * wpb + wid; q < npairs; q += nwaves) {
-    int i, j;
-    if (m_tri > 0) {
-      tri_pair(q, m_tri, i, j);
-    } else {
-      i = (int)(q / nb);
-      j = (int)(q - (int64_t)i * nb);
-    }
+    // the triangle form walks the full square in the block form's order and
+    // skips j <= i: consecutive workgroups (spread over the XCDs in turn)
+    // then keep taking the same residues of j, so each XCD's L2 holds a
+    // fixed share of the rows
+    const int i = (int)(q / nb);
+    const int j = (int)(q - (int64_t)i * nb);
+    if (m_tri > 0 && j <= i) continue;
     const int16_t* ra = recA + (size_t)i * (k + 2);
     const int16_t* rb = recB + (size_t)j * (k + 2);
     const int nea = ra[k], neb = rb[k];
@@ -119,61 +129,91 @@ __global__ __launch_bounds__(256) void distance_kernel(const int16_t* __restrict
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // class orders in registers: lane holds entries lane, lane + 64, ...
       int oa[KW], ob[KW];
+      // per owned class c = lane + 64 w: 0xffff - c while the class is free in
+      // that pass (all ones then), 0 once matched or when c >= k
+      uint32_t lowc[KW], gateB[KW], gateA[KW];
 #pragma unroll
       for (int w = 0; w < KW; ++w) {
         const int t = lane + kWave * w;
         oa[w] = t < k ? ra[t] : 0;
         ob[w] = t < k ? rb[t] : 0;
+        lowc[w] = 0xffffu - (uint32_t)t;
+        gateB[w] = gateA[w] = t < k ? 0xffffffffu : 0u;
       }
-      uint32_t takenB = 0u, takenA = 0u;  // bit w: class lane + 64 w already matched
+      // every lane loaded the same counts: make that visible to the compiler
+      const int na_ = __builtin_amdgcn_readfirstlane(nea), nb_ = __builtin_amdgcn_readfirstlane(neb);
       uint32_t sab = 0u, sba = 0u;
-      const int steps = nea > neb ? nea : neb;
+      const int steps = na_ > nb_ ? na_ : nb_;
       for (int t = 0; t < steps; ++t) {
         const int tw = t / kWave, tl = t % kWave;
-        int ro = 0, co = 0;
+        uint32_t ro = 0u, co = 0u;
 #pragma unroll
         for (int w = 0; w < KW; ++w)
           if (w == tw) {
-            ro = (int)readlane((uint32_t)oa[w], tl);
-            co = (int)readlane((uint32_t)ob[w], tl);
+            ro = readlane((uint32_t)oa[w], tl);
+            co = readlane((uint32_t)ob[w], tl);
           }
-        // pass over A: row ro of M, lanes own the columns (classes of B)
-        // pass over B: column co of M, lanes own the rows (classes of A)
+        // pass over A: row ro of M, lanes own the columns (classes of B);
+        // pass over B: column co of M, lanes own the rows (classes of A).  A
+        // key (overlap << 16 | 0xffff - class) with overlap 0 never beats one
+        // with a positive overlap, so a zero maximum overlap means "no match".
         uint32_t ka = 0u, kb = 0u;
 #pragma unroll
         for (int w = 0; w < KW; ++w) {
-          const int c = lane + kWave * w;
-          if (c < k) {
-            const uint32_t va = (t < nea && !((takenB >> w) & 1u)) ? (uint32_t)h16[ro * k + c] : 0u;
-            const uint32_t vb = (t < neb && !((takenA >> w) & 1u)) ? (uint32_t)h16[c * k + co] : 0u;
-            ka = max(ka, va ? (va << 16) | (0xffffu - (uint32_t)c) : 0u);
-            kb = max(kb, vb ? (vb << 16) | (0xffffu - (uint32_t)c) : 0u);
-          }
+          int c = lane + kWave * w;
+          c = c < k ? c : k - 1;  // in-table address; the gate drops the value
+          const uint32_t va = h16[ro * (uint32_t)k + (uint32_t)c];
+          const uint32_t vb = h16[(uint32_t)c * (uint32_t)k + co];
+          ka = max(ka, ((va << 16) | lowc[w]) & gateB[w]);
+          kb = max(kb, ((vb << 16) | lowc[w]) & gateA[w]);
         }
-        const uint32_t ma = wave_max_u32(ka), mb = wave_max_u32(kb);
-        if (ma) {
+        if (t >= na_) ka = 0u;
+        if (t >= nb_) kb = 0u;
+        wave_max2(ka, kb);
+        const uint32_t ma = ka, mb = kb;
+        if (ma >> 16) {
           sab += ma >> 16;
-          const int c = 0xffff - (int)(ma & 0xffffu);
-          if ((c & (kWave - 1)) == lane) takenB |= 1u << (c / kWave);
+          const uint32_t c = 0xffffu - (ma & 0xffffu);
+#pragma unroll
+          for (int w = 0; w < KW; ++w)
+            if (c == (uint32_t)(lane + kWave * w)) gateB[w] = 0u;
         }
-        if (mb) {
+        if (mb >> 16) {
           sba += mb >> 16;
-          const int c = 0xffff - (int)(mb & 0xffffu);
-          if ((c & (kWave - 1)) == lane) takenA |= 1u << (c / kWave);
+          const uint32_t c = 0xffffu - (mb & 0xffffu);
+#pragma unroll
+          for (int w = 0; w < KW; ++w)
+            if (c == (uint32_t)(lane + kWave * w)) gateA[w] = 0u;
         }
       }
       d = n - (int32_t)(sab > sba ? sab : sba);
     }
-    if (lane == 0) {
-      out[(size_t)i * ld + j] = d;
-      if (m_tri > 0) out[(size_t)j * ld + i] = d;
-    }
+    if (lane == 0) out[(size_t)i * ld + j] = d;
   }
 }
 
 __global__ __launch_bounds__(256) void diag_zero_kernel(int32_t m, int32_t* __restrict__ out, int64_t ld) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) out[(size_t)i * ld + i] = 0;
+}
+
+// out[i][j] = out[j][i] for i > j: 32 x 32 tiles of the strict upper
+// triangle read by rows into LDS and written transposed by rows, so both
+// sides stay coalesced
+__global__ __launch_bounds__(256) void mirror_kernel(int32_t m, int32_t* __restrict__ out, int64_t ld) {
+  __shared__ int32_t tile[32][33];
+  const int ti = blockIdx.y, tj = blockIdx.x;  // destination tile (ti, tj), ti >= tj
+  if (ti < tj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int r = ty; r < 32; r += 8) {  // source tile (tj, ti): rows tj*32 + r, columns ti*32 + tx
+    const int si = tj * 32 + r, sj = ti * 32 + tx;
+    tile[r][tx] = (si < m && sj < m && si < sj) ? out[(size_t)si * ld + sj] : 0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {  // destination rows ti*32 + r, columns tj*32 + tx
+    const int di = ti * 32 + r, dj = tj * 32 + tx;
+    if (di < m && dj < m && di > dj) out[(size_t)di * ld + dj] = tile[tx][r];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -292,11 +332,15 @@ __global__ __launch_bounds__(256) void nearest_kernel(const int32_t* __restrict_
 
 using namespace dlm;
 
+static int distance_pairs(const int16_t* a, const int16_t* b, const int16_t* recA, const int16_t* recB, int32_t na,
+                          int32_t nb, int32_t tri, int32_t n, int32_t k, int64_t npairs, int32_t* out, int64_t ld,
+                          hipStream_t s);
+
 extern "C" {
 
 int dlm_partition_distance(int32_t n, int32_t k, const int16_t* a, int32_t na, const int16_t* b, int32_t nb,
                            int32_t tri, int32_t* out, int64_t ld, void* workspace, void* stream) {
-  if (n < 1 || n > 32767 || k < 1 || k > kMaxDistK || na < 0 || nb < 0 || (tri != 0 && tri != 1))
+  if (n < 1 || n > 32767 || k < 1 || k > kMaxDistK || na < 0 || nb < 0 || tri < 0 || tri > 2)
     return set_error(DLM_E_INVAL, "dlm_partition_distance: n=%d k=%d na=%d nb=%d tri=%d", n, k, na, nb, tri);
   if (tri && (a != b || na != nb))
     return set_error(DLM_E_INVAL, "dlm_partition_distance: tri needs the same rows on both sides");
@@ -312,12 +356,23 @@ int dlm_partition_distance(int32_t n, int32_t k, const int16_t* a, int32_t na, c
     hipLaunchKernelGGL(class_order_kernel, dim3(nb), dim3(kWave), 0, s, b, n, k, recB);
     DLM_HIP(hipGetLastError());
   }
-  const int64_t npairs = tri ? (int64_t)na * (na - 1) / 2 : (int64_t)na * nb;
+  const int64_t npairs = tri ? (na > 1 ? (int64_t)na * na : 0) : (int64_t)na * nb;  // triangle: slots of the square
   if (tri) {
     hipLaunchKernelGGL(diag_zero_kernel, dim3((na + 255) / 256), dim3(256), 0, s, na, out, ld);
     DLM_HIP(hipGetLastError());
   }
   if (npairs == 0) return DLM_OK;
+  const int rc = distance_pairs(a, b, recA, recB, na, nb, tri, n, k, npairs, out, ld, s);
+  if (rc != DLM_OK || tri != 1) return rc;
+  const unsigned tiles = (unsigned)((na + 31) / 32);
+  hipLaunchKernelGGL(mirror_kernel, dim3(tiles, tiles), dim3(256), 0, s, na, out, ld);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+static int distance_pairs(const int16_t* a, const int16_t* b, const int16_t* recA, const int16_t* recB, int32_t na,
+                          int32_t nb, int32_t tri, int32_t n, int32_t k, int64_t npairs, int32_t* out, int64_t ld,
+                          hipStream_t s) {
   const uint32_t wave_bytes = 4u * hist_words(k);
   int wpb = (int)(65536u / wave_bytes);  // up to 4 waves and 64 KB of LDS per workgroup
   wpb = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);

@@ -119,7 +119,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         if diversity:
             pool, nxt = pools
             A.partition_distance(cols, k, off, out=pool[:pop, pop:])
-            A.partition_distance(off, k, out=pool[pop:, pop:])
+            A.partition_distance(off, k, out=pool[pop:, pop:], upper_only=True)
             pick, _ = A.spacing_update(f, r["f_best"], pool, pop, graph.n // 10)
             A.gather_distances(pool, pick, out=nxt[:pop, :pop])
             cols, f = A.gather_pool(cols, f, off, r["f_best"], pick)

@@ -69,6 +69,20 @@ def test_distance_triangle(dlm, dev, k, n, m):
     assert (got == ref).all(), np.argwhere(got != ref)[:5]
 
 
+@pytest.mark.parametrize("m", [2, 33, 70])
+def test_distance_upper_triangle_only(dlm, dev, m):
+    rng = np.random.default_rng(40 + m)
+    rows = colourings(rng, m, 90, 9)
+    out = torch.full((m, m), -7, dtype=torch.int32, device="cuda")
+    say(f"distance upper triangle m={m}")
+    dlm.partition_distance(cuda(rows), 9, out=out, upper_only=True)
+    got = out.cpu().numpy()
+    ref = dv.distance_matrix(rows, rows, 9)
+    iu = np.triu_indices(m, 1)
+    assert (got[iu] == ref[iu]).all() and (np.diag(got) == 0).all()
+    assert (got[np.tril_indices(m, -1)] == -7).all()
+
+
 def test_relabelled_copies_are_zero(dlm, dev):
     rng = np.random.default_rng(11)
     a = colourings(rng, 16, 333, 40)
@@ -102,10 +116,12 @@ def test_pool_blocks_in_place(dlm, dev):
     pool = torch.full((2 * p, 2 * p), -7, dtype=torch.int32, device="cuda")
     say("distance pool blocks")
     dlm.partition_distance(cuda(old), k, cuda(new), out=pool[:p, p:])
-    dlm.partition_distance(cuda(new), k, out=pool[p:, p:])
+    dlm.partition_distance(cuda(new), k, out=pool[p:, p:], upper_only=True)
     got = pool.cpu().numpy()
     assert (got[:p, p:] == dv.distance_matrix(old, new, k)).all()
-    assert (got[p:, p:] == dv.distance_matrix(new, new, k)).all()
+    iu = np.triu_indices(p)
+    assert (got[p:, p:][iu] == dv.distance_matrix(new, new, k)[iu]).all()
+    assert (got[p:, p:][np.tril_indices(p, -1)] == -7).all()
     assert (got[:, :p] == -7).all()
 
 
