@@ -8,7 +8,8 @@ does.  It shares no code with the HIP kernels.
 ``scorer.py`` the FP64 numpy reference of the offspring scorer;
 ``brute.py`` exhaustive solvers for tiny graphs used as pins;
 ``diversity.py`` the partition distance, spacing update and nearest
-neighbours of the population (plain Python).
+neighbours of the population (plain Python); ``reduce.py`` the step from k to
+k - 1 colours of the decreasing-k driver.
 """
 from __future__ import annotations
 
