@@ -136,7 +136,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
-                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity"])
+                    choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity",
+                             "decreasing", "popsweep"])
+    ap.add_argument("--pops", default="256,1024,4096,16384", help="popsweep: population sizes")
+    ap.add_argument("--passes", type=int, default=3,
+                    help="popsweep: budget = this many local-search passes of the largest population")
     ap.add_argument("--cutoff", type=float, default=300.0,
                     help="memetic1000: wall-clock limit per loop (seconds)")
     ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
@@ -181,6 +185,10 @@ def main():
         return bench_scorer(args, workload("memetic1000"), dlm, torch)
     if args.workload == "diversity":
         return bench_diversity(args, workload("gnp500"), dlm, torch)
+    if args.workload == "popsweep":
+        return bench_popsweep(args, workload("wvcp300"), workload("memetic1000"), dlm, torch)
+    if args.workload == "decreasing":
+        return bench_decreasing(args, workload("gnp500"), workload("memetic1000"), dlm, torch)
     w = workload(args.workload)
     if args.workload == "uneven64":
         return bench_uneven(args, w, dlm, torch)
@@ -437,6 +445,82 @@ def bench_scorer(args, w, dlm, torch):
            "roofline_mfma": {"bound": "mfma", "achieved": mfma_f / (inf_ms * 1e-3) / 1e12, "peak": 2500.0,
                              "unit": "TFLOP/s", "frac": mfma_f / (inf_ms * 1e-3) / 1e12 / 2500.0,
                              "train_achieved": tr_tflops}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_popsweep(args, w, wm, dlm, torch):
+    """Sensitivity to the population size at a fixed total number of local-
+    search iterations (the study of the paper's Section 4 on the WVCP): the
+    learned memetic loop on the weighted G(300, 0.3) of wvcp300, greedy
+    start, 10 rounds of 10 n iterations per local search, for each
+    population p as many generations as the budget allows (budget = passes
+    x the largest p local searches).  Reports the best legal weighted score
+    reached by each p and its trajectory."""
+    from paper_2109_05948_amd import memetic
+    from workloads.scorer_init import scorer_weights
+    g = w.graphs[0]
+    G = dlm.Graph.from_csr(g)
+    pops = [int(x) for x in args.pops.split(",")]
+    per_search = 10 * g.n * 10
+    budget = args.passes * max(pops) * per_search
+    e = wm.extra
+    out_runs = []
+    for p in pops:
+        passes = budget // (p * per_search)
+        log(f"popsweep p={p}: {passes} local-search passes ({passes - 1} generations)")
+        r = memetic.run(G, 0, p, 10 * g.n, learned=True, seed=int(args.seeds.split(",")[0]),
+                        cutoff_s=args.cutoff, max_generations=max(passes - 1, 0),
+                        children_per_pair=e["children_per_pair"], keep_frac=e["keep_frac"],
+                        scorer_params=scorer_weights(g.n, seed=0), batch=min(e["batch"], p),
+                        epochs=e["epochs"], lr=e["lr"], weighted=True, rounds=10, log=log,
+                        diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
+        out_runs.append({"population": p, "generations": r.generations, "best_wscore": r.best,
+                         "wall_s": r.wall, "moves": r.tabu_moves,
+                         "history": [[h[0], h[1], h[2]] for h in r.history]})
+        log(f"popsweep p={p}: best {r.best} after {r.generations} generations, {r.wall:.1f} s")
+    best = min(out_runs, key=lambda x: (x["best_wscore"], x["population"]))
+    out = {"metric": "best legal weighted score at a fixed tabu budget vs population size (lower is better)",
+           "value": best["best_wscore"], "unit": "weighted score", "n_gpus": 1, "higher_is_better": False,
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "popsweep", "graph": "G(n=300, p=0.3) seed 0, weights U{1..100}",
+                      "populations": pops, "iters_per_search": per_search, "budget_iters": budget,
+                      "best_population": best["population"]},
+           "runs": out_runs}
+    print(json.dumps(out), flush=True)
+
+
+def bench_decreasing(args, w, wm, dlm, torch):
+    """COL by decreasing k (Section 2.7) on G(500, 0.5), the shape of
+    DSJC500.5: the memetic loop from k (default 53), k dropping by one after
+    every legal colouring, population 8192, 128 n tabu iterations per
+    offspring, the memetic1000 generation settings, one overall cutoff.
+    value = the smallest k coloured legally; the record lists when each k
+    was first solved."""
+    from paper_2109_05948_amd import memetic
+    from workloads.scorer_init import scorer_weights
+    g = w.graphs[0]
+    G = dlm.Graph.from_csr(g)
+    k0 = args.k or 53
+    pop, T, e = args.pop or w.pop, 128 * g.n, wm.extra
+    res = {}
+    for name in args.loops.split(","):
+        sd = int(args.seeds.split(",")[0])
+        log(f"decreasing {name} from k={k0} seed={sd}")
+        r = memetic.decreasing_k(G, k0, pop, T, learned=(name == "learned"), seed=sd, cutoff_s=args.cutoff,
+                                 scorer_params=scorer_weights(g.n, seed=0), log=log,
+                                 children_per_pair=e["children_per_pair"], keep_frac=e["keep_frac"],
+                                 batch=e["batch"], epochs=e["epochs"], lr=e["lr"],
+                                 diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
+        res[name] = {"best_k": r.best_k, "found": [[k, t] for k, t in r.found], "wall_s": r.wall,
+                     "generations": [x.generations for x in r.runs]}
+    best = [v["best_k"] for v in res.values() if v["best_k"] is not None]
+    out = {"metric": "smallest k coloured legally by decreasing-k COL within the cutoff (lower is better)",
+           "value": min(best) if best else None, "unit": "colours", "n_gpus": 1, "higher_is_better": False,
+           "vs_baseline": None, "dtype": "int16+bf16", "data": "synthetic",
+           "config": {"workload": "decreasing", "graph": "G(n=500, p=0.5) seed 0", "k_start": k0,
+                      "population": pop, "iters_per_tabu": T, "cutoff_s": args.cutoff,
+                      "diversity_neighbours": args.diversity},
+           "loops": res}
     print(json.dumps(out), flush=True)
 
 

@@ -335,6 +335,16 @@ int dlm_random_pairs(int32_t pop, uint64_t seed, uint32_t gen, int32_t* pairs_de
 int dlm_select_groups(const float* scores_dev, int32_t groups, int32_t K, int32_t mode, uint64_t seed,
                       uint32_t gen, int32_t* idx_dev, void* stream);
 
+/* The step from k to k - 1 colours of the decreasing-k driver (Section
+ * 2.7: once a legal k-colouring is found, k drops by one), in place on
+ * colors_dev (int16 [pop][n]): each row's smallest class (ties by smaller
+ * colour) is dissolved, its vertex v takes colour floor(w0 (k - 1) / 2^32),
+ * w0 = word 0 of Philox(seed; row, step, v, 0x8000000B), and colours above
+ * the dissolved one move down by one.  A row with a colour outside [0, k)
+ * becomes all -1.  2 <= k <= 32767, n <= 32767. */
+int dlm_reduce_colours(int16_t* colors_dev, int32_t pop, int32_t n, int32_t k, uint64_t seed, uint32_t step,
+                       void* stream);
+
 /* Keep the pop best of parents (indices 0..pop-1) and offspring (indices
  * pop..2pop-1) by score ascending, ties by index: out_dev int16[pop][n] and
  * f_out_dev int32[pop] in rank order.  workspace_dev: 24 * pop bytes. */

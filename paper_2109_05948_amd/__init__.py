@@ -21,6 +21,7 @@ from ._abi import (  # noqa: F401
     pop_update,
     probe_lds_bandwidth,
     random_pairs,
+    reduce_colours,
     standardize,
     gpx_batch,
     select,

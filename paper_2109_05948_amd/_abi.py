@@ -34,7 +34,7 @@ EXPORTS = [
     "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
     "dlm_multi_plan_destroy", "dlm_multi_autotune", "dlm_probe_lds_bandwidth",
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
-    "dlm_nearest", "dlm_select_groups",
+    "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
             L.dlm_gather_pool.argtypes = [P, P, I32, P, P, I32, I32, P, I32, P, P, P]
             L.dlm_nearest.argtypes = [P, I64, I32, I32, P, P]
             L.dlm_select_groups.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P]
+            L.dlm_reduce_colours.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -493,6 +494,14 @@ def select_groups(scores: torch.Tensor | None, groups: int, K: int, mode: str = 
                                                         seed & (2**64 - 1), gen & 0xffffffff, _ptr(out),
                                                         _stream(stream)))
     return out
+
+
+def reduce_colours(colors: torch.Tensor, k: int, seed: int, step: int, stream=None):
+    """dlm_reduce_colours: k -> k - 1 colours, in place on colors (int16 [pop, n])."""
+    _dev(colors, torch.int16, "colors")
+    _check("dlm_reduce_colours", lib().dlm_reduce_colours(_ptr(colors), colors.shape[0], colors.shape[1], k,
+                                                          seed & (2**64 - 1), step & 0xffffffff, _stream(stream)))
+    return colors
 
 
 def nearest(dist: torch.Tensor, K: int, p: int | None = None, stream=None):

@@ -7,6 +7,7 @@ namespace dlm {
 
 constexpr uint32_t kDomPair = 0x80000009u;
 constexpr uint32_t kDomSelGroup = 0x8000000Au;
+constexpr uint32_t kDomReduce = 0x8000000Bu;
 
 __global__ __launch_bounds__(256) void gather_rows_kernel(const int16_t* __restrict__ src, int32_t rows,
                                                           int32_t n, const int32_t* __restrict__ idx,
@@ -128,6 +129,44 @@ __global__ __launch_bounds__(256) void select_groups_kernel(const float* __restr
   idx[g] = g * K + best;
 }
 
+// k -> k - 1 colours, one workgroup per row (in place): the class sizes in
+// LDS, the smallest class (ties by colour) by a block minimum of
+// size << 15 | colour, then its vertices redrawn and the classes above it
+// moved down by one.  A row with a colour outside [0, k) becomes all -1.
+__global__ __launch_bounds__(256) void reduce_colours_kernel(int16_t* __restrict__ colors, int32_t n, int32_t k,
+                                                             Key key, uint32_t step) {
+  extern __shared__ __align__(16) uint32_t sizes[];  // k counters
+  __shared__ uint32_t wmin[4];
+  const int r = blockIdx.x, tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  int16_t* row = colors + (size_t)r * n;
+  for (int c = tid; c < k; c += blockDim.x) sizes[c] = 0u;
+  __syncthreads();
+  int bad = 0;
+  for (int v = tid; v < n; v += blockDim.x) {
+    const int c = row[v];
+    if (c < 0 || c >= k)
+      bad = 1;
+    else
+      atomicAdd(&sizes[c], 1u);
+  }
+  if (__syncthreads_or(bad)) {
+    for (int v = tid; v < n; v += blockDim.x) row[v] = -1;
+    return;
+  }
+  uint32_t best = 0xffffffffu;
+  for (int c = tid; c < k; c += blockDim.x) best = min(best, (sizes[c] << 15) | (uint32_t)c);
+  best = wave_min_u32(best);
+  if (lane == 0) wmin[wid] = best;
+  __syncthreads();
+  best = min(min(wmin[0], wmin[1]), min(wmin[2], wmin[3]));
+  const int gone = (int)(best & 0x7fffu);
+  for (int v = tid; v < n; v += blockDim.x) {
+    const int c = row[v];
+    row[v] = (int16_t)(c == gone ? (int)lemire(philox_w0((uint32_t)r, step, (uint32_t)v, kDomReduce, key), (uint32_t)(k - 1))
+                                 : c - (c > gone));
+  }
+}
+
 }  // namespace dlm
 
 using namespace dlm;
@@ -169,6 +208,21 @@ int dlm_select_groups(const float* scores, int32_t groups, int32_t K, int32_t mo
   if (!idx || (mode == DLM_SELECT_TOP && !scores)) return set_error(DLM_E_INVAL, "dlm_select_groups: null buffer");
   hipLaunchKernelGGL(select_groups_kernel, dim3((groups + 255) / 256), dim3(256), 0, (hipStream_t)stream, scores,
                      groups, K, mode, make_key(seed), gen, idx);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_reduce_colours(int16_t* colors, int32_t pop, int32_t n, int32_t k, uint64_t seed, uint32_t step,
+                       void* stream) {
+  if (pop < 0 || n < 1 || n > 32767 || k < 2 || k > 32767)
+    return set_error(DLM_E_INVAL, "dlm_reduce_colours: pop=%d n=%d k=%d", pop, n, k);
+  if (pop == 0) return DLM_OK;
+  if (!colors) return set_error(DLM_E_INVAL, "dlm_reduce_colours: null buffer");
+  const size_t lds = (size_t)k * 4u;
+  DLM_HIP(hipFuncSetAttribute((const void*)reduce_colours_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  hipLaunchKernelGGL(reduce_colours_kernel, dim3(pop), dim3(256), lds, (hipStream_t)stream, colors, n, k,
+                     make_key(seed), step);
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }

@@ -49,14 +49,27 @@ class MemeticResult:
     scorer_loss: list = field(default_factory=list)
     colors: object = None  # final population (device int16 [pop, n]) and its scores
     f: object = None
+    scorer_params: dict | None = None  # the learned loop's scorer at the end
 
 
 def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int = 0,
         cutoff_s: float = 600.0, max_generations: int = 1 << 30, children_per_pair: int = 4,
         keep_frac: float = 0.25, scorer_params: dict | None = None, batch: int = 1024,
         epochs: int = 5, lr: float = 1e-3, block: int = 0, table: str = "auto",
-        log=None, diversity: bool = False, neighbours: int = 16) -> MemeticResult:
+        log=None, diversity: bool = False, neighbours: int = 16,
+        init_colors: torch.Tensor | None = None, weighted: bool = False, rounds: int = 10,
+        target: int | None = None) -> MemeticResult:
+    """One loop of Algorithm 1.  With ``weighted`` it solves the WVCP
+    (Section 2.2): the start is the greedy colouring (k = 0 takes the largest
+    number of colours it uses), the local search is Algorithm 2 with
+    ``iters`` iterations per round over ``rounds`` rounds, and an
+    individual's score is its best legal weighted score.  The loop stops when
+    the best score reaches ``target`` (default 0 for k-COL, none for WVCP),
+    at ``max_generations`` or at the cutoff; ``time_to_legal`` is then the
+    time the target was reached."""
     dev = torch.device("cuda", torch.cuda.current_device())
+    if target is None:
+        target = -1 if weighted else 0
     if diversity:
         children_per_pair, keep_frac = neighbours, 1.0 / neighbours
         if not 1 <= neighbours < pop:
@@ -69,15 +82,30 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         raise ValueError("the learned loop needs initial scorer parameters")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cols, _ = A.init_population(graph, k, pop, seed=seed)
-    r = A.tabu_batch(graph, cols, k, iters, seed ^ SEED_TABU, ind_base=0, block=block, table=table)
-    f = r["f_best"].clone()
-    moves = int(r["stats"][:, 0].sum().item())
+    if init_colors is not None:
+        if tuple(init_colors.shape) != (pop, graph.n):
+            raise ValueError(f"init_colors must be [{pop}, {graph.n}]")
+        cols = init_colors.clone()
+    elif weighted:
+        cols, k_used = A.init_population(graph, k, pop, seed=seed, mode="greedy")
+        k = k or int(k_used.max().item())
+    else:
+        cols, _ = A.init_population(graph, k, pop, seed=seed)
+
+    def search(colors, ind_base):  # the local search, in place; returns (scores, moves)
+        if weighted:
+            o = A.wvcp_batch(graph, colors, k, iters, rounds, seed ^ SEED_TABU, ind_base=ind_base, block=block)
+            return o["best_legal"], int(o["stats"][:, 0].sum().item())
+        o = A.tabu_batch(graph, colors, k, iters, seed ^ SEED_TABU, ind_base=ind_base, block=block, table=table)
+        return o["f_best"], int(o["stats"][:, 0].sum().item())
+
+    f, moves = search(cols, 0)
+    f = f.clone()
     best = int(f.min().item())
     res = MemeticResult(learned, best, 0, None, 0.0)
     now = time.perf_counter() - t0
     res.history.append((now, 0, best, float(f.float().mean().item())))
-    if best == 0:
+    if best <= target:
         res.time_to_legal = now
     sc = A.Scorer(graph.n, k, scorer_params, max_batch=batch) if learned else None
     off = torch.empty((nsel, graph.n), dtype=torch.int16, device=dev)
@@ -89,7 +117,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         first = torch.arange(pop, dtype=torch.int32, device=dev).repeat_interleave(neighbours)
     ind_next = pop
     gen = 0
-    while best > 0 and gen < max_generations and time.perf_counter() - t0 < cutoff_s:
+    while best > target and gen < max_generations and time.perf_counter() - t0 < cutoff_s:
         gen += 1
         if diversity:
             nn = A.nearest(pools[0], neighbours, p=pop)
@@ -109,34 +137,81 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
             idx = A.select(None, nchild, nsel, "random", seed=seed ^ SEED_SEL, gen=gen)
         A.gather_rows(children, idx, out=off)
         A.gather_rows(children, idx, out=start)
-        r = A.tabu_batch(graph, off, k, iters, seed ^ SEED_TABU, ind_base=ind_next, block=block,
-                         table=table)
+        f_off, gen_moves = search(off, ind_next)
         ind_next += nsel
         if learned:
-            tgt = A.standardize(r["f_best"])
+            tgt = A.standardize(f_off)
             loss = sc.train(start, tgt, batch=batch, epochs=epochs, lr=lr)
             res.scorer_loss.append(float(loss[-1].item()))
         if diversity:
             pool, nxt = pools
             A.partition_distance(cols, k, off, out=pool[:pop, pop:])
             A.partition_distance(off, k, out=pool[pop:, pop:], upper_only=True)
-            pick, _ = A.spacing_update(f, r["f_best"], pool, pop, graph.n // 10)
+            pick, _ = A.spacing_update(f, f_off, pool, pop, graph.n // 10)
             A.gather_distances(pool, pick, out=nxt[:pop, :pop])
-            cols, f = A.gather_pool(cols, f, off, r["f_best"], pick)
+            cols, f = A.gather_pool(cols, f, off, f_off, pick)
             pools = [nxt, pool]
         else:
-            cols, f = A.pop_update(cols, f, off, r["f_best"])
-        moves += int(r["stats"][:, 0].sum().item())
+            cols, f = A.pop_update(cols, f, off, f_off)
+        moves += gen_moves
         best = int(f.min().item())
         now = time.perf_counter() - t0
         res.history.append((now, gen, best, float(f.float().mean().item())))
         if log:
             log(f"[{'learned' if learned else 'plain'}] gen {gen} t={now:.1f}s best={best} "
                 f"mean={res.history[-1][3]:.2f}")
-        if best == 0:
+        if best <= target:
             res.time_to_legal = now
     torch.cuda.synchronize()
     res.best, res.generations, res.tabu_moves = best, gen, moves
     res.colors, res.f = cols, f
+    if sc is not None:
+        res.scorer_params = sc.params()
+    res.wall = time.perf_counter() - t0
+    return res
+
+
+@dataclass
+class DecreasingResult:
+    best_k: int | None
+    found: list  # (k, seconds from the start) of every legal k-colouring, in order
+    legal: dict  # k -> a legal k-colouring (host int16 [n])
+    wall: float
+    runs: list = field(default_factory=list)  # the MemeticResult of each k
+
+
+def decreasing_k(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int = 0,
+                 cutoff_s: float = 600.0, scorer_params: dict | None = None, log=None,
+                 **kw) -> DecreasingResult:
+    """COL as a series of k-COL problems (Section 2.7): once a legal
+    k-colouring is found, k drops by one and the search continues from the
+    same population, moved to k - 1 colours by dissolving each individual's
+    smallest class (dlm_reduce_colours); the learned loop keeps its scorer
+    (fresh Adam moments).  Stops when a k is not solved within the overall
+    cutoff; the last k solved bounds the chromatic number from above."""
+    t0 = time.perf_counter()
+    res = DecreasingResult(None, [], {}, 0.0)
+    cols, params, step = None, scorer_params, 0
+    while k >= 2:
+        start = time.perf_counter() - t0
+        left = cutoff_s - start
+        if left <= 0:
+            break
+        r = run(graph, k, pop, iters, learned, seed=seed + step, cutoff_s=left, scorer_params=params,
+                init_colors=cols, log=log, **kw)
+        res.runs.append(r)
+        if r.time_to_legal is None:
+            break
+        res.found.append((k, start + r.time_to_legal))
+        i = int(torch.argmin(r.f).item())
+        res.legal[k] = r.colors[i].cpu().numpy()
+        res.best_k = k
+        if log:
+            log(f"[decreasing] legal {k}-colouring at {res.found[-1][1]:.1f} s")
+        cols = A.reduce_colours(r.colors, k, seed, step=k - 1)
+        params = r.scorer_params if learned else params
+        k -= 1
+        step += 1
+    torch.cuda.synchronize()
     res.wall = time.perf_counter() - t0
     return res

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from workloads.graphs import gnp
+from workloads.graphs import gnp, planted_partite
 from workloads.scorer_init import scorer_weights
 
 pytestmark = pytest.mark.gpu
@@ -135,3 +135,60 @@ def test_short_memetic_loop_diversity(dlm, dev, learned):
     assert (conf == res.f).all()
     if learned and res.generations:
         assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()
+
+
+def test_reduce_colours(dlm, dev):
+    from oracle import reduce as rd
+    rng = np.random.default_rng(8)
+    for pop, n, k in ((1, 1, 2), (9, 57, 5), (300, 500, 49), (4, 900, 300)):
+        rows = rng.integers(0, k, size=(pop, n)).astype(np.int16)
+        if pop > 3:
+            rows[3, 5] = k  # an invalid row
+        say(f"reduce_colours pop={pop} n={n} k={k}")
+        got = dlm.reduce_colours(torch.from_numpy(rows).cuda(), k, seed=31, step=k - 1).cpu().numpy()
+        assert (got == rd.reduce_colours(rows, k, seed=31, step=k - 1)).all()
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_decreasing_k(dlm, dev, learned):
+    """Section 2.7 on a planted 6-partite graph from k = 9: every k found
+    legal is one below the last, each reported colouring is legal with k
+    colours, and k = 6 (the planted partition) is reached."""
+    from paper_2109_05948_amd import memetic
+    g, _ = planted_partite(150, 6, 0.5, seed=2)
+    G = dlm.Graph.from_csr(g)
+    say(f"decreasing k learned={learned}")
+    res = memetic.decreasing_k(G, 9, 32, 3000, learned, seed=4, cutoff_s=90, max_generations=30,
+                               scorer_params=scorer_weights(g.n, seed=0), batch=32, epochs=1)
+    ks = [k for k, _ in res.found]
+    assert ks[:4] == [9, 8, 7, 6] and ks == list(range(9, 9 - len(ks), -1))
+    assert all(t2 >= t1 for (_, t1), (_, t2) in zip(res.found, res.found[1:]))
+    for k, col in res.legal.items():
+        assert col.min() >= 0 and col.max() < k
+        conf, _ = dlm.evaluate(G, torch.from_numpy(col[None, :]).cuda(), k)
+        assert int(conf.item()) == 0
+    assert res.best_k == ks[-1] <= 6
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_weighted_memetic_loop(dlm, dev, learned):
+    """The loop on the WVCP (Section 2.2): greedy start, Algorithm 2 as the
+    local search; the best legal weighted score never rises, and every
+    reported score is the weighted score of a legal colouring in the
+    population."""
+    from paper_2109_05948_amd import memetic
+    from workloads.graphs import uniform_weights
+    g = gnp(90, 0.3, seed=4)
+    g = g.with_weights(uniform_weights(90, 1, 100, seed=5))
+    G = dlm.Graph.from_csr(g)
+    say(f"weighted memetic learned={learned}")
+    res = memetic.run(G, 0, 32, 10 * g.n, learned=learned, seed=2, cutoff_s=60, max_generations=3,
+                      scorer_params=scorer_weights(g.n, seed=0), batch=32, epochs=1, weighted=True, rounds=3)
+    bests = [h[2] for h in res.history]
+    assert all(b2 <= b1 for b1, b2 in zip(bests, bests[1:]))
+    assert res.generations == 3 and res.time_to_legal is None
+    k = int(res.colors.max().item()) + 1
+    conf, ws = dlm.evaluate(G, res.colors, k, weighted=True)
+    legal = (res.f != 0x7fffffff)
+    assert legal.any() and (conf[legal] == 0).all()
+    assert (ws[legal] == res.f[legal]).all()
