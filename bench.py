@@ -42,8 +42,8 @@ METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned
 # --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads
 # for a 1 GiB device-to-device copy.  Valid only for the kernel sources they
 # were taken on (digest below) and the same table and block; otherwise null.
-MEASURED_TRAFFIC = {"sources_sha256": "a49607525a91de2372d5e4777ebedc77474e481e770d02b3a6f4189487964094",
-                    "table": "split8", "block": 256, "bytes": 85512207530}  # profiles/tabucol_split8_gnp500.md
+MEASURED_TRAFFIC = {"sources_sha256": "cf4e5663af7ecbe6c68f5b9f43f23ce5679c2bae93ee9f4692b0252fc633a637",
+                    "table": "split8", "block": 256, "bytes": 84982992446}  # profiles/tabucol_split8_gnp500.md
 KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd/csrc/tabucol.hip",
                   "paper_2109_05948_amd/csrc/dlm_common.h")
 

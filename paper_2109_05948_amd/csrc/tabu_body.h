@@ -417,6 +417,7 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
   const int trace_cap = a.trace_cap, T = a.T;
   const Key key = a.key;
   const uint32_t ten_num = (uint32_t)a.ten_num, ten_den = (uint32_t)a.ten_den, ten_rand = (uint32_t)a.ten_rand;
+  const uint32_t den_inv = 0xffffffffu / ten_den;
   const TabuLayout L = tabu_layout(n, k, NW, Tab::kLdsBytes);
   Tab tab = Tab::make(smem + L.tab, gtab);
   uint32_t* cg = reinterpret_cast<uint32_t*>(smem + L.cg);
@@ -856,46 +857,63 @@ __device__ __forceinline__ void tabu_individual(const TabuArgs& a, int li, unsig
         const int e = rs + tid + r * BLOCK;
         nb[r] = e < re ? col_idx[e] : -1;
       }
+      // v*'s own state, by wave 0 while the row loads are in flight.  None of
+      // it touches what the neighbour updates touch: they change rows u != v*
+      // of the table, cg[u], pos[u] and other list slots (the shared
+      // tombstone count is an atomic); the snapshot above was taken first.
+      if (wid == 0) {
+        const uint32_t Lt = readlane(Lreg, t & 63);
+        if (lane == 0) {
+          // tenure term floor(num * f / den), capped; the product fits 32 bits in
+          // practice, and then the quotient is a multiply by the reciprocal
+          // 0xffffffff / den (low by at most 2) and two corrections
+          const uint64_t prod = (uint64_t)ten_num * (uint32_t)fnew;
+          uint32_t ttf;
+          if (prod <= 0xffffffffull) {
+            const uint32_t x = (uint32_t)prod;
+            ttf = __umulhi(x, den_inv);
+            uint32_t rem = x - ttf * ten_den;
+            if (rem >= ten_den) {
+              rem -= ten_den;
+              ++ttf;
+            }
+            if (rem >= ten_den) ++ttf;
+          } else {
+            ttf = (uint32_t)std::min<uint64_t>(prod / ten_den, kTenureCap + 1);
+          }
+          const bool capped = ttf > (uint32_t)kTenureCap;
+          if (capped) ttf = kTenureCap;
+          tab.set_tabu(vs * kp + old, trel + Lt + ttf);
+          tab.set_tabu(vs * kp + cs, Tab::kInf);
+          const uint32_t gnew = tab.gamma(vs * kp + cs);
+          cg[vs] = (uint32_t)cs | (gnew << 16);
+          if (Tab::kBounded) {
+            csize[old] -= 1u;
+            csize[cs] += 1u;
+          }
+          if (gnew == 0u) {
+            list[pos[vs]] = kTomb;
+            pos[vs] = kNoPos;
+            atomicAdd(&sc[1], 1u);
+          }
+          if (trace && t < trace_cap) {
+            gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
+            tr[0] = vs | (cs << 16);
+            tr[1] = fnew;
+          }
+          st_conf += (uint64_t)C;
+          st_deg += (uint64_t)(re - rs);
+          st_ties += gcnt > 1u;
+          st_cap += capped;
+          fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, fnew);
+        }
+      }
 #pragma unroll
       for (int r = 0; r < kPre; ++r)
         if (rs + r * BLOCK < re) update(nb[r], nb[r] >= 0);  // uniform per round: ballots see the whole wave
       for (int e0 = rs + kPre * BLOCK; e0 < re; e0 += BLOCK) {
         const int e = e0 + tid;
         update(e < re ? col_idx[e] : 0, e < re);
-      }
-    }
-    if (wid == 0) {
-      const uint32_t Lt = readlane(Lreg, t & 63);
-      if (lane == 0) {
-        // tenure term floor(num * f / den), capped; the product fits 32 bits in practice
-        const uint64_t prod = (uint64_t)ten_num * (uint32_t)fnew;
-        uint32_t ttf = prod <= 0xffffffffull ? (uint32_t)prod / ten_den
-                                             : (uint32_t)std::min<uint64_t>(prod / ten_den, kTenureCap + 1);
-        const bool capped = ttf > (uint32_t)kTenureCap;
-        if (capped) ttf = kTenureCap;
-        tab.set_tabu(vs * kp + old, trel + Lt + ttf);
-        tab.set_tabu(vs * kp + cs, Tab::kInf);
-        const uint32_t gnew = tab.gamma(vs * kp + cs);
-        cg[vs] = (uint32_t)cs | (gnew << 16);
-        if (Tab::kBounded) {
-          csize[old] -= 1u;
-          csize[cs] += 1u;
-        }
-        if (gnew == 0u) {
-          list[pos[vs]] = kTomb;
-          pos[vs] = kNoPos;
-          atomicAdd(&sc[1], 1u);
-        }
-        if (trace && t < trace_cap) {
-          gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
-          tr[0] = vs | (cs << 16);
-          tr[1] = fnew;
-        }
-        st_conf += (uint64_t)C;
-        st_deg += (uint64_t)(re - rs);
-        st_ties += gcnt > 1u;
-        st_cap += capped;
-        fp = fnv_step(fp, (uint32_t)vs, (uint32_t)cs, fnew);
       }
     }
     f = fnew;

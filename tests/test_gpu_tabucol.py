@@ -296,3 +296,17 @@ def test_many_rounds_per_lane(dlm, dev, block):
     say(f"tabu matching3000 k=2000 block={block} global16")
     gpu = gpu_run(dlm, g, starts, k, T, 5, table="global16", block=block)
     compare(gpu, ref, range(pop), f"matching3000 block={block}")
+
+
+@pytest.mark.parametrize("num,den", [(7, 3), (5, 1), (32767, 7)])
+def test_tenure_slopes(dlm, dev, num, den):
+    """Other tenure slopes num/den: the quotient floor(num * f / den) is
+    taken through a reciprocal of den in the kernel; trajectories must
+    still equal the oracle's."""
+    g = gnp(150, 0.5, seed=6)
+    k, T, pop = 17, 3000, 6
+    starts = oracle.init_random(g.n, k, pop, seed=8)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=12, ten_num=num, ten_den=den)
+    say(f"tabu tenure {num}/{den}")
+    gpu = gpu_run(dlm, g, starts, k, T, 12, ten_num=num, ten_den=den, table="split8")
+    compare(gpu, ref, range(pop), f"tenure {num}/{den}")
