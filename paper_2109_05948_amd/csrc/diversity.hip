@@ -131,60 +131,79 @@ __global__ __launch_bounds__(256) void distance_kernel(const int16_t* __restrict
       int oa[KW], ob[KW];
       // per owned class c = lane + 64 w: 0xffff - c while the class is free in
       // that pass (all ones then), 0 once matched or when c >= k
-      uint32_t lowc[KW], gateB[KW], gateA[KW];
+      // per owned class c = lane + 64 w: lowc = 0xffff - c, and a byte
+      // selector that builds the key (overlap << 16 | lowc) in one v_perm_b32
+      // while the class is free in that pass, or 0 once matched or for c >= k
+      constexpr uint32_t kSelKey = 0x05040100u, kSelZero = 0x0c0c0c0cu;
+      uint32_t lowc[KW], selB[KW], selA[KW];
 #pragma unroll
       for (int w = 0; w < KW; ++w) {
         const int t = lane + kWave * w;
         oa[w] = t < k ? ra[t] : 0;
         ob[w] = t < k ? rb[t] : 0;
         lowc[w] = 0xffffu - (uint32_t)t;
-        gateB[w] = gateA[w] = t < k ? 0xffffffffu : 0u;
+        selB[w] = selA[w] = t < k ? kSelKey : kSelZero;
       }
       // every lane loaded the same counts: make that visible to the compiler
       const int na_ = __builtin_amdgcn_readfirstlane(nea), nb_ = __builtin_amdgcn_readfirstlane(neb);
       uint32_t sab = 0u, sba = 0u;
-      const int steps = na_ > nb_ ? na_ : nb_;
-      for (int t = 0; t < steps; ++t) {
-        const int tw = t / kWave, tl = t % kWave;
-        uint32_t ro = 0u, co = 0u;
+      auto order_at = [&](const int (&o)[KW], int t) {
+        uint32_t x = 0u;
 #pragma unroll
         for (int w = 0; w < KW; ++w)
-          if (w == tw) {
-            ro = readlane((uint32_t)oa[w], tl);
-            co = readlane((uint32_t)ob[w], tl);
-          }
-        // pass over A: row ro of M, lanes own the columns (classes of B);
-        // pass over B: column co of M, lanes own the rows (classes of A).  A
-        // key (overlap << 16 | 0xffff - class) with overlap 0 never beats one
-        // with a positive overlap, so a zero maximum overlap means "no match".
-        uint32_t ka = 0u, kb = 0u;
+          if (w == t / kWave) x = readlane((uint32_t)o[w], t % kWave);
+        return x;
+      };
+      // pass over A: row ro of M, lanes own the columns (classes of B); pass
+      // over B: column co of M, lanes own the rows (classes of A).  A key with
+      // overlap 0 never beats one with a positive overlap, so a zero maximum
+      // overlap means "no match".
+      auto key_a = [&](uint32_t ro) {
+        uint32_t ka = 0u;
 #pragma unroll
         for (int w = 0; w < KW; ++w) {
-          int c = lane + kWave * w;
-          c = c < k ? c : k - 1;  // in-table address; the gate drops the value
-          const uint32_t va = h16[ro * (uint32_t)k + (uint32_t)c];
-          const uint32_t vb = h16[(uint32_t)c * (uint32_t)k + co];
-          ka = max(ka, ((va << 16) | lowc[w]) & gateB[w]);
-          kb = max(kb, ((vb << 16) | lowc[w]) & gateA[w]);
+          const int c0 = lane + kWave * w;
+          const uint32_t c = (uint32_t)(c0 < k ? c0 : k - 1);  // in-table address; the selector drops the value
+          ka = max(ka, __builtin_amdgcn_perm((uint32_t)h16[ro * (uint32_t)k + c], lowc[w], selB[w]));
         }
-        if (t >= na_) ka = 0u;
-        if (t >= nb_) kb = 0u;
+        return ka;
+      };
+      auto key_b = [&](uint32_t co) {
+        uint32_t kb = 0u;
+#pragma unroll
+        for (int w = 0; w < KW; ++w) {
+          const int c0 = lane + kWave * w;
+          const uint32_t c = (uint32_t)(c0 < k ? c0 : k - 1);
+          kb = max(kb, __builtin_amdgcn_perm((uint32_t)h16[c * (uint32_t)k + co], lowc[w], selA[w]));
+        }
+        return kb;
+      };
+      auto take = [&](uint32_t m, uint32_t& sum, uint32_t (&sel)[KW]) {
+        if (m >> 16) {
+          sum += m >> 16;
+          const uint32_t c = 0xffffu - (m & 0xffffu);
+#pragma unroll
+          for (int w = 0; w < KW; ++w)
+            if (c == (uint32_t)(lane + kWave * w)) sel[w] = kSelZero;
+        }
+      };
+      const int both = na_ < nb_ ? na_ : nb_;
+      int t = 0;
+      for (; t < both; ++t) {  // both passes, their maxima interleaved
+        uint32_t ka = key_a(order_at(oa, t)), kb = key_b(order_at(ob, t));
         wave_max2(ka, kb);
-        const uint32_t ma = ka, mb = kb;
-        if (ma >> 16) {
-          sab += ma >> 16;
-          const uint32_t c = 0xffffu - (ma & 0xffffu);
-#pragma unroll
-          for (int w = 0; w < KW; ++w)
-            if (c == (uint32_t)(lane + kWave * w)) gateB[w] = 0u;
-        }
-        if (mb >> 16) {
-          sba += mb >> 16;
-          const uint32_t c = 0xffffu - (mb & 0xffffu);
-#pragma unroll
-          for (int w = 0; w < KW; ++w)
-            if (c == (uint32_t)(lane + kWave * w)) gateA[w] = 0u;
-        }
+        take(ka, sab, selB);
+        take(kb, sba, selA);
+      }
+      for (; t < na_; ++t) {  // the longer pass alone
+        uint32_t ka = key_a(order_at(oa, t)), kz = 0u;
+        wave_max2(ka, kz);
+        take(ka, sab, selB);
+      }
+      for (; t < nb_; ++t) {
+        uint32_t kb = key_b(order_at(ob, t)), kz = 0u;
+        wave_max2(kb, kz);
+        take(kb, sba, selA);
       }
       d = n - (int32_t)(sab > sba ? sab : sba);
     }
