@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference for the "
