@@ -6,6 +6,7 @@ does.  It shares no code with the HIP kernels.
 
 ``oracle.c`` holds the search algorithms (plain C, built with gcc);
 ``scorer.py`` the FP64 numpy reference of the offspring scorer;
+``invnet.py`` the FP64 reference of the paper's colour-invariant network;
 ``brute.py`` exhaustive solvers for tiny graphs used as pins;
 ``diversity.py`` the partition distance, spacing update and nearest
 neighbours of the population (plain Python); ``reduce.py`` the step from k to
