@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
                     choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity",
-                             "decreasing", "popsweep"])
+                             "decreasing", "popsweep", "invnet"])
     ap.add_argument("--pops", default="256,1024,4096,16384", help="popsweep: population sizes")
     ap.add_argument("--passes", type=int, default=3,
                     help="popsweep: budget = this many local-search passes of the largest population")
@@ -185,6 +185,8 @@ def main():
         return bench_scorer(args, workload("memetic1000"), dlm, torch)
     if args.workload == "diversity":
         return bench_diversity(args, workload("gnp500"), dlm, torch)
+    if args.workload == "invnet":
+        return bench_invnet(args, workload("gnp500"), dlm, torch)
     if args.workload == "popsweep":
         return bench_popsweep(args, workload("wvcp300"), workload("memetic1000"), dlm, torch)
     if args.workload == "decreasing":
@@ -600,6 +602,82 @@ def bench_diversity(args, w, dlm, torch):
                         "ops_per_pair": n + 2 * k * k}}
     print(json.dumps(out), flush=True)
 
+
+def invnet_flops(n, k, widths, b, train):
+    """GEMM flops of one pass over b colourings: per layer the class rows
+    (b k x l_in x l_out) and the class means (b x l_in x l_out); training adds
+    the weight gradients of both and, above the first layer, the input
+    gradients of both."""
+    f, l_in = 0.0, n
+    for j, l_out in enumerate(widths):
+        per = 2.0 * (b * k + b) * l_in * l_out
+        f += per
+        if train:
+            f += per * (2 if j > 0 else 1)
+        l_in = l_out
+    return f
+
+
+def bench_invnet(args, w, dlm, torch):
+    """The paper's colour-invariant network for k-COL at the G(500, 0.5),
+    k = 49 shape (hidden widths 10n, 5n, 2n x 5, n, n // 2; 44.3 M
+    trainables): one generation's scoring of 8192 colourings (evaluation, in
+    chunks of 512) and one training epoch over 8192 (colouring, score) pairs
+    at the paper's batch of 100 (82 Adam steps).  Inputs are Philox-random
+    colourings and standard-normal targets, resident before timing; weights
+    from the seeded fully connected initialisation.
+
+    Every product is a BF16 GEMM with FP32 accumulation (rocBLAS); the rest
+    (one-hot input, class means, normalisation, activation, loss, Adam) runs
+    on the library's kernels.  The roofline is the dense BF16 MFMA peak."""
+    from workloads.invnet_init import col_widths, invnet_weights
+    g, k = w.graphs[0], w.k[0]
+    n, p = g.n, args.pop or w.pop
+    widths = col_widths(n)
+    batch, chunk = 100, 512
+    G = dlm.Graph.from_csr(g)
+    net = dlm.InvNet(n, k, widths, invnet_weights(n, widths, seed=0), max_batch=chunk)
+    col, _ = dlm.init_population(G, k, p, seed=31)
+    gen = torch.Generator().manual_seed(12)
+    tgt = torch.randn(p, generator=gen).to("cuda")
+    scores = torch.empty(p, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    for s_ in range(args.warmup):
+        log(f"warmup step {s_}")
+        net.forward(col, out=scores)
+        net.train(col, tgt, batch, 1)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        ev[s_][0].record(stream)
+        net.forward(col, out=scores)
+        ev[s_][1].record(stream)
+        losses = net.train(col, tgt, batch, 1)
+        ev[s_][2].record(stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in ev]))
+    tr_ms = float(np.mean([b.elapsed_time(c) for _, b, c in ev]))
+    inf_f = invnet_flops(n, k, widths, p, False)
+    tr_f = invnet_flops(n, k, widths, p, True)
+    inf_tf = inf_f / (inf_ms * 1e-3) / 1e12
+    tr_tf = tr_f / (tr_ms * 1e-3) / 1e12
+    log(f"timed {args.steps} steps in {dt:.3f} s; scoring {inf_ms:.1f} ms ({inf_tf:.0f} TFLOP/s), "
+        f"training epoch {tr_ms:.1f} ms ({tr_tf:.0f} TFLOP/s); last loss {float(losses[-1].item()):.4f}")
+    out = {"metric": "colourings scored/s (colour-invariant network, k-COL depth)",
+           "value": p / (inf_ms * 1e-3), "unit": "colourings/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
+           "config": {"workload": "invnet", "graph": "G(n=500, p=0.5) seed 0", "k": k, "widths": widths,
+                      "colourings": p, "batch": batch, "eval_chunk": chunk, "epochs": 1},
+           "inference_ms": inf_ms, "train_epoch_ms": tr_ms,
+           "train_pairs_per_s": p / (tr_ms * 1e-3),
+           "roofline": {"bound": "mfma", "achieved": inf_tf, "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": inf_tf / 2500.0, "traffic": None, "kernel": "whole evaluation pass",
+                        "flops_per_colouring": inf_f / p, "train_achieved": tr_tf,
+                        "train_frac": tr_tf / 2500.0, "train_flops_per_pair": tr_f / p}}
+    print(json.dumps(out), flush=True)
 
 if __name__ == "__main__":
     main()

@@ -482,6 +482,68 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
                      void* stream);
 
 /* ------------------------------------------------------------------------
+ * The paper's colour-invariant network (Section 2.3) as a scorer: a
+ * colouring S = (V_1 .. V_k) enters as its k class indicator vectors over
+ * the n vertices; layer j maps the k class rows X_i (width l_in) to
+ *   Z_i = X_i Lambda_j + rho(X) Gamma_j + beta_j,  rho(X) = (1/k) sum_i X_i
+ * hidden layers: X'_i = LReLU_0.2(BN(Z)_i), with the invariant batch
+ * normalisation over the batch and all k classes per feature (eps 1e-5,
+ * learnable scale gamma_j and shift mu_j per feature, running estimates with
+ * momentum 0.1 and the unbiased variance); the last layer has width 1 and
+ * the output is (1/k) sum_i Z_i.  Every product is a GEMM with BF16 operands
+ * and FP32 accumulation (rocBLAS); everything else runs in FP32 on kernels of
+ * this library, reductions in a fixed order.
+ *
+ * widths: nl layer widths (hidden ..., 1).  params_host: FP32, per layer
+ * Lambda [l_in][l_out], Gamma [l_in][l_out], beta [l_out], then for hidden
+ * layers gamma [l_out], mu [l_out] (row-major; the trainables), followed by
+ * the running mean [l_out] and running variance [l_out] of every hidden layer
+ * in order; copied at creation.  max_batch bounds the colourings of one
+ * training step and the chunk of one evaluation pass; the network allocates
+ * its activations for that many (about 6 (max_batch k) sum(widths) + 6
+ * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767.
+ * ---------------------------------------------------------------------- */
+typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, rocBLAS handle */
+
+int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, const float* params_host,
+                      int32_t max_batch, dlm_invnet** out);
+int dlm_invnet_destroy(dlm_invnet* s);
+/* sizes of the two parts of the packed layout above */
+int dlm_invnet_num_params(const dlm_invnet* s, int64_t* trainable, int64_t* running);
+/* copy the FP32 trainables, then the running estimates (packed layout), to params_dev */
+int dlm_invnet_get_params(const dlm_invnet* s, float* params_dev, void* stream);
+
+/*
+ * Evaluation: out_dev[c] = f(colouring c) for `count` colourings
+ * (colors_dev int16[count][n], colours in [0, k)), the normalisation taken
+ * from the running estimates; chunks of max_batch.  A colour outside [0, k)
+ * gives that vertex no class.
+ */
+int dlm_invnet_forward(dlm_invnet* s, const int16_t* colors_dev, int32_t count, float* out_dev, void* stream);
+
+/*
+ * Gradient of the mean squared error (1/count) sum_c (f_c - t_c)^2 on one
+ * batch (1 <= count <= max_batch), the normalisation from the batch's own
+ * statistics, written to grad_dev (float[trainable], may be NULL); loss_dev
+ * (float[1], may be NULL) receives the loss.  Neither the trainables nor the
+ * running estimates change.
+ */
+int dlm_invnet_grad(dlm_invnet* s, const int16_t* colors_dev, const float* targets_dev, int32_t count,
+                    float* grad_dev, float* loss_dev, void* stream);
+
+/*
+ * Training: `epochs` passes over the `count` pairs in consecutive batches of
+ * `batch` (the last may be smaller); each batch is a training-mode forward
+ * (which also moves the running estimates), the MSE gradient and one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction counted over the
+ * network's lifetime) on the FP32 trainables, then a BF16 re-cast of every
+ * Lambda and Gamma.  loss_dev (float[epochs * ceil(count/batch)], may be
+ * NULL) receives each step's loss before its update.
+ */
+int dlm_invnet_train(dlm_invnet* s, const int16_t* colors_dev, const float* targets_dev, int32_t count,
+                     int32_t batch, int32_t epochs, float lr, float* loss_dev, void* stream);
+
+/* ------------------------------------------------------------------------
  * Measurement helper (not part of the search): sustained LDS read bandwidth
  * of the whole device in bytes/s, from a kernel that streams conflict-free
  * 16-byte LDS reads on every resident workgroup for `rounds` passes over a

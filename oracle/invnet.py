@@ -19,6 +19,10 @@ scalars; per-feature vectors are taken here, as in the batch normalisation
 it adapts), running estimates with momentum 0.1 (unbiased variance) used in
 evaluation.  Training minimises the mean squared error with Adam (beta1 0.9,
 beta2 0.999, eps 1e-8, learning rate 1e-3 in the paper).
+
+Every matrix product takes its two operands through q (the identity unless
+given): a test can pass a perturbation of the size of a rounding to measure
+how sensitive each result is to the precision of the products' operands.
 """
 from __future__ import annotations
 
@@ -67,17 +71,22 @@ def trainable(P: dict) -> list[str]:
     return names
 
 
-def forward(P: dict, colors: np.ndarray, k: int, train: bool):
+def _identity(a):
+    return a
+
+
+def forward(P: dict, colors: np.ndarray, k: int, train: bool, q=None):
     """Returns (f of shape (b,), cache).  In training mode BN uses the batch
     statistics and the cache holds what the backward pass needs; the running
     estimates are not touched here (see update_running)."""
+    q = q or _identity
     x = one_hot(np.asarray(colors), k)
     b = x.shape[0]
     cache = {"x": [], "zhat": [], "std": [], "y": [], "mean": [], "var": []}
     nl = len(P["widths"])
     for j in range(nl):
         rho = x.mean(axis=1, keepdims=True)
-        z = x @ P[f"L{j}"] + rho @ P[f"G{j}"] + P[f"b{j}"]
+        z = q(x) @ q(P[f"L{j}"]) + q(rho) @ q(P[f"G{j}"]) + P[f"b{j}"]
         cache["x"].append(x)
         if j == nl - 1:
             return z[:, :, 0].mean(axis=1), cache
@@ -99,8 +108,9 @@ def forward(P: dict, colors: np.ndarray, k: int, train: bool):
     raise AssertionError("no output layer")
 
 
-def backward(P: dict, cache: dict, df: np.ndarray, k: int) -> dict:
+def backward(P: dict, cache: dict, df: np.ndarray, k: int, q=None) -> dict:
     """Gradients of sum_c df[c] * f[c] with respect to every trainable."""
+    q = q or _identity
     nl = len(P["widths"])
     grads = {}
     b = df.shape[0]
@@ -109,12 +119,12 @@ def backward(P: dict, cache: dict, df: np.ndarray, k: int) -> dict:
         x = cache["x"][j]
         rho = x.mean(axis=1, keepdims=True)
         du = dz.sum(axis=1, keepdims=True)  # the rho term reaches every class row
-        grads[f"L{j}"] = np.einsum("cil,cim->lm", x, dz)
-        grads[f"G{j}"] = np.einsum("cil,cim->lm", rho, du)
+        grads[f"L{j}"] = np.einsum("cil,cim->lm", q(x), q(dz))
+        grads[f"G{j}"] = np.einsum("cil,cim->lm", q(rho), q(du))
         grads[f"b{j}"] = dz.sum(axis=(0, 1))
         if j == 0:
             break
-        dx = dz @ P[f"L{j}"].T + (du @ P[f"G{j}"].T) / k
+        dx = q(dz) @ q(P[f"L{j}"]).T + (q(du) @ q(P[f"G{j}"]).T) / k
         # through LReLU and the invariant BN of layer j - 1
         y = cache["y"][j - 1]
         dy = dx * np.where(y > 0, 1.0, SLOPE)
@@ -139,7 +149,7 @@ def update_running(P: dict, cache: dict, b: int, k: int) -> None:
 
 
 def train(P: dict, colors: np.ndarray, targets: np.ndarray, k: int, batch: int, epochs: int,
-          lr: float = 1e-3, state: dict | None = None) -> tuple[list, dict]:
+          lr: float = 1e-3, state: dict | None = None, q=None) -> tuple[list, dict]:
     """Consecutive mini-batches, MSE loss, Adam; returns (losses, Adam state)."""
     b1, b2, eps = 0.9, 0.999, 1e-8
     st = state or {"t": 0, **{f"M_{nm}": np.zeros_like(P[nm]) for nm in trainable(P)},
@@ -150,9 +160,9 @@ def train(P: dict, colors: np.ndarray, targets: np.ndarray, k: int, batch: int, 
         for s in range(0, n_rows, batch):
             c = colors[s:s + batch]
             t = np.asarray(targets[s:s + batch], dtype=np.float64)
-            f, cache = forward(P, c, k, train=True)
+            f, cache = forward(P, c, k, train=True, q=q)
             losses.append(float(((f - t) ** 2).mean()))
-            g = backward(P, cache, 2.0 * (f - t) / c.shape[0], k)
+            g = backward(P, cache, 2.0 * (f - t) / c.shape[0], k, q=q)
             update_running(P, cache, c.shape[0], k)
             st["t"] += 1
             for nm in trainable(P):

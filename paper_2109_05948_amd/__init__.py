@@ -7,6 +7,7 @@ arguments.  Import fails loudly when the library has not been built.
 from ._abi import (  # noqa: F401
     DlmError,
     Graph,
+    InvNet,
     MultiBatch,
     NSTATS,
     Scorer,
@@ -27,6 +28,7 @@ from ._abi import (  # noqa: F401
     select,
     select_groups,
     init_population,
+    invnet_names,
     lib,
     tabu_batch,
     wvcp_batch,

@@ -34,7 +34,9 @@ EXPORTS = [
     "dlm_multi_plan_create", "dlm_multi_plan_launch", "dlm_multi_plan_info",
     "dlm_multi_plan_destroy", "dlm_multi_autotune", "dlm_probe_lds_bandwidth",
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
-    "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours",
+    "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours", "dlm_invnet_create",
+    "dlm_invnet_destroy", "dlm_invnet_num_params", "dlm_invnet_get_params", "dlm_invnet_forward",
+    "dlm_invnet_grad", "dlm_invnet_train",
 ]
 
 
@@ -96,6 +98,13 @@ def lib():
             L.dlm_nearest.argtypes = [P, I64, I32, I32, P, P]
             L.dlm_select_groups.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P]
             L.dlm_reduce_colours.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P]
+            L.dlm_invnet_create.argtypes = [I32, I32, I32, P, P, I32, C.POINTER(P)]
+            L.dlm_invnet_destroy.argtypes = [P]
+            L.dlm_invnet_num_params.argtypes = [P, C.POINTER(I64), C.POINTER(I64)]
+            L.dlm_invnet_get_params.argtypes = [P, P, P]
+            L.dlm_invnet_forward.argtypes = [P, P, I32, P, P]
+            L.dlm_invnet_grad.argtypes = [P, P, P, I32, P, P, P]
+            L.dlm_invnet_train.argtypes = [P, P, P, I32, I32, I32, C.c_float, P, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -356,6 +365,98 @@ class Scorer:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().dlm_scorer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def invnet_names(widths) -> tuple[list[str], list[str]]:
+    """Names of the packed dlm_invnet layout: the trainables per layer (Lambda
+    L, Gamma G, beta b, and for hidden layers the scale g and shift m), then
+    the running mean rm and variance rv of every hidden layer."""
+    train, run = [], []
+    for j in range(len(widths)):
+        train += [f"L{j}", f"G{j}", f"b{j}"]
+        if j < len(widths) - 1:
+            train += [f"g{j}", f"m{j}"]
+            run += [f"rm{j}", f"rv{j}"]
+    return train, run
+
+
+class InvNet:
+    """dlm_invnet: the colour-invariant network (FP32 trainables, BF16 GEMM
+    operands, invariant batch normalisation, Adam)."""
+
+    def __init__(self, n: int, k: int, widths, params: dict, max_batch: int = 64):
+        self.widths = [int(w) for w in widths]
+        self.train_names, self.run_names = invnet_names(self.widths)
+        names = self.train_names + self.run_names
+        flat = np.concatenate([np.ascontiguousarray(params[nm], dtype=np.float32).reshape(-1)
+                               for nm in names])
+        w = np.asarray(self.widths, dtype=np.int32)
+        h = C.c_void_p()
+        _check("dlm_invnet_create", lib().dlm_invnet_create(n, k, len(self.widths), _ptr(w), _ptr(flat),
+                                                            max_batch, C.byref(h)))
+        self._h, self.n, self.k, self.max_batch = h, n, k, max_batch
+        self.shapes = {nm: np.asarray(params[nm]).shape for nm in names}
+        tr, rn = C.c_int64(), C.c_int64()
+        _check("dlm_invnet_num_params", lib().dlm_invnet_num_params(h, C.byref(tr), C.byref(rn)))
+        self.num_trainable, self.num_running = tr.value, rn.value
+        assert self.num_trainable + self.num_running == flat.size
+
+    def unpack(self, flat: np.ndarray, names=None) -> dict:
+        out, o = {}, 0
+        for nm in (names if names is not None else self.train_names + self.run_names):
+            sz = int(np.prod(self.shapes[nm]))
+            out[nm] = flat[o:o + sz].reshape(self.shapes[nm])
+            o += sz
+        return out
+
+    def params(self, stream=None) -> dict:
+        buf = torch.empty(self.num_trainable + self.num_running, dtype=torch.float32, device="cuda")
+        _check("dlm_invnet_get_params", lib().dlm_invnet_get_params(self._h, _ptr(buf), _stream(stream)))
+        return self.unpack(buf.cpu().numpy())
+
+    def forward(self, colors: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """dlm_invnet_forward (evaluation) -> float32 [count]."""
+        _dev(colors, torch.int16, "colors")
+        cnt = colors.shape[0]
+        out = out if out is not None else torch.empty(cnt, dtype=torch.float32, device=colors.device)
+        _check("dlm_invnet_forward", lib().dlm_invnet_forward(self._h, _ptr(colors), cnt, _ptr(out),
+                                                              _stream(stream)))
+        return out
+
+    def grad(self, colors: torch.Tensor, targets: torch.Tensor, stream=None):
+        """dlm_invnet_grad -> (flat FP32 gradient of the batch MSE, loss)."""
+        _dev(colors, torch.int16, "colors")
+        _dev(targets, torch.float32, "targets")
+        g = torch.empty(self.num_trainable, dtype=torch.float32, device=colors.device)
+        loss = torch.empty(1, dtype=torch.float32, device=colors.device)
+        _check("dlm_invnet_grad", lib().dlm_invnet_grad(self._h, _ptr(colors), _ptr(targets),
+                                                        colors.shape[0], _ptr(g), _ptr(loss),
+                                                        _stream(stream)))
+        return g, loss
+
+    def train(self, colors: torch.Tensor, targets: torch.Tensor, batch: int, epochs: int,
+              lr: float = 1e-3, stream=None) -> torch.Tensor:
+        """dlm_invnet_train -> per-step losses."""
+        _dev(colors, torch.int16, "colors")
+        _dev(targets, torch.float32, "targets")
+        cnt = colors.shape[0]
+        steps = epochs * ((cnt + batch - 1) // batch)
+        loss = torch.empty(max(steps, 1), dtype=torch.float32, device=colors.device)
+        _check("dlm_invnet_train", lib().dlm_invnet_train(self._h, _ptr(colors), _ptr(targets), cnt,
+                                                          batch, epochs, C.c_float(lr), _ptr(loss),
+                                                          _stream(stream)))
+        return loss[:steps]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dlm_invnet_destroy(self._h)
             self._h = None
 
     def __del__(self):

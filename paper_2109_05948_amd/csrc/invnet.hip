@@ -1,0 +1,620 @@
+// The paper's colour-invariant network (Section 2.3) and its training.
+//
+// A colouring enters as k one-hot class vectors over the n vertices; a batch
+// of B colourings is an (B k) x n matrix, one row per (colouring, class).
+// Layer j maps rows of width l_in to l_out:
+//   Z = X Lambda + broadcast_over_classes(R Gamma) + beta,  R = class mean of X
+//   hidden:  X' = LReLU_0.2(BN(Z)), BN over the B k rows per feature (batch
+//            statistics in training, running estimates with momentum 0.1 in
+//            evaluation; learnable scale and shift per feature)
+//   output (width 1):  f = class mean of Z.
+// Every product is a plain GEMM (BF16 operands, FP32 accumulation and
+// output) and goes to rocBLAS; the one-hot input, class means, broadcasts,
+// normalisation, activation, loss, their backward steps and Adam are the
+// kernels below.  All reductions run in a fixed order.
+#include <rocblas/rocblas.h>
+
+#include <vector>
+
+#include "dlm_common.h"
+
+namespace dlm {
+
+constexpr float kInvSlope = 0.2f;
+constexpr float kBnEps = 1e-5f;
+constexpr float kBnMomentum = 0.1f;
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {  // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// X0[(c k + i) n + v] = 1 if colour i holds vertex v in colouring c
+__global__ __launch_bounds__(256) void inv_onehot_kernel(const int16_t* __restrict__ colors, int32_t n, int32_t k,
+                                                         uint16_t* __restrict__ x0) {
+  const int64_t row = blockIdx.x;  // c k + i
+  const int c = (int)(row / k), i = (int)(row - (int64_t)c * k);
+  for (int v = threadIdx.x; v < n; v += blockDim.x)
+    x0[row * n + v] = colors[(size_t)c * n + v] == i ? (uint16_t)0x3f80u : (uint16_t)0u;
+}
+
+// R[c][f] = (1/k) sum_i X[c k + i][f], BF16 out
+__global__ __launch_bounds__(256) void inv_class_mean_kernel(const uint16_t* __restrict__ x, int32_t k, int32_t l,
+                                                             uint16_t* __restrict__ r) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  float s = 0.f;
+  for (int i = 0; i < k; ++i) s += from_bf16(x[((size_t)c * k + i) * l + f]);
+  r[(size_t)c * l + f] = to_bf16(s / (float)k);
+}
+
+// Forward normalisation statistics, per (colouring c, feature f): over the k
+// class rows of v = z + u[c] + beta, the mean and the sum of squared
+// deviations (two passes; the second re-reads the block's rows from cache).
+__global__ __launch_bounds__(256) void inv_fwd_stats_kernel(const float* __restrict__ z, const float* __restrict__ u,
+                                                            const float* __restrict__ beta, int32_t k, int32_t l,
+                                                            float* __restrict__ pmean, float* __restrict__ pm2) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  const float add = u[(size_t)c * l + f] + beta[f];
+  const float* zc = z + (size_t)c * k * l + f;
+  float s = 0.f;
+  for (int i = 0; i < k; ++i) s += zc[(size_t)i * l];
+  const float m = s / (float)k + add;
+  float q = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float d = zc[(size_t)i * l] + add - m;
+    q += d * d;
+  }
+  pmean[(size_t)c * l + f] = m;
+  pm2[(size_t)c * l + f] = q;
+}
+
+// The B groups of k rows merged in colouring order (equal group sizes):
+// mean = average of the group means, M2 = sum of the group M2 plus
+// k sum (group mean - mean)^2; biased variance M2 / (B k).  With update, the
+// running estimates move by the momentum towards (mean, unbiased variance).
+__global__ __launch_bounds__(256) void inv_fwd_stats_final_kernel(const float* __restrict__ pmean,
+                                                                  const float* __restrict__ pm2, int32_t B,
+                                                                  int32_t k, int32_t l, float* __restrict__ mean,
+                                                                  float* __restrict__ var, float* __restrict__ rm,
+                                                                  float* __restrict__ rv, int32_t update) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  float s = 0.f;
+  for (int c = 0; c < B; ++c) s += pmean[(size_t)c * l + f];
+  const float m = s / (float)B;
+  float q = 0.f, d2 = 0.f;
+  for (int c = 0; c < B; ++c) {
+    const float d = pmean[(size_t)c * l + f] - m;
+    q += pm2[(size_t)c * l + f];
+    d2 += d * d;
+  }
+  const float N = (float)B * (float)k;
+  const float v = (q + (float)k * d2) / N;
+  mean[f] = m;
+  var[f] = v;
+  if (update) {
+    rm[f] = (1.f - kBnMomentum) * rm[f] + kBnMomentum * m;
+    rv[f] = (1.f - kBnMomentum) * rv[f] + kBnMomentum * v * (N / (N - 1.f));
+  }
+}
+
+// Normalise, scale, shift and activate the k class rows of colouring c:
+// X'[c k + i][f] = LReLU((z + u[c] + beta - mean) / sqrt(var + eps) gamma + mu)
+// in BF16, and the class mean of the next layer R'[c][f] from those values.
+__global__ __launch_bounds__(256) void inv_fwd_apply_kernel(const float* __restrict__ z, const float* __restrict__ u,
+                                                            const float* __restrict__ beta,
+                                                            const float* __restrict__ mean,
+                                                            const float* __restrict__ var,
+                                                            const float* __restrict__ gamma,
+                                                            const float* __restrict__ mu, int32_t k, int32_t l,
+                                                            uint16_t* __restrict__ xn, uint16_t* __restrict__ rn) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
+  const size_t base = (size_t)c * k * l + f;
+  float r = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+    const float y = zh * g + sh;
+    const uint16_t xb = to_bf16(y > 0.f ? y : kInvSlope * y);
+    xn[base + (size_t)i * l] = xb;
+    r += from_bf16(xb);
+  }
+  rn[(size_t)c * l + f] = to_bf16(r / (float)k);
+}
+
+// output layer: f[c] = mean_i z[c k + i] + u[c] + beta
+__global__ __launch_bounds__(256) void inv_output_kernel(const float* __restrict__ z, const float* __restrict__ u,
+                                                         const float* __restrict__ beta, int32_t k, int32_t B,
+                                                         float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= B) return;
+  float s = 0.f;
+  for (int i = 0; i < k; ++i) s += z[(size_t)c * k + i];
+  out[c] = s / (float)k + u[c] + beta[0];
+}
+
+// MSE on one batch: df[c] = 2 (f - t) / B, loss = mean (f - t)^2 (one block, fixed order)
+__global__ __launch_bounds__(256) void inv_mse_kernel(const float* __restrict__ f, const float* __restrict__ t,
+                                                      int32_t B, float* __restrict__ df, float* __restrict__ loss) {
+  __shared__ float part[256];
+  float s = 0.f;
+  for (int c = threadIdx.x; c < B; c += 256) {
+    const float d = f[c] - t[c];
+    df[c] = 2.f * d / (float)B;
+    s += d * d;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) *loss = part[0] / (float)B;
+}
+
+// output layer backward: dz (width 1) = df[c] / k on every class row, dU = df
+__global__ __launch_bounds__(256) void inv_out_bwd_kernel(const float* __restrict__ df, int32_t k, int32_t B,
+                                                          uint16_t* __restrict__ dzb, uint16_t* __restrict__ dub,
+                                                          float* __restrict__ dbeta) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (int64_t)B * k) dzb[e] = to_bf16(df[e / k] / (float)k);
+  if (e < B) dub[e] = to_bf16(df[e]);
+  if (e == 0) {
+    float s = 0.f;
+    for (int c = 0; c < B; ++c) s += df[c];
+    dbeta[0] = s;
+  }
+}
+
+// Backward through LReLU and the normalisation of a hidden layer, pass 1,
+// per (colouring c, feature f): with zhat recomputed from the stored z and
+// dY = (dX + dR[c] / k) LReLU'(zhat gamma + mu) over the k class rows (the
+// dR / k term is the class-mean path of the layer above), the partial sums
+// of dY and dY zhat; summed over colourings these are the gradients of mu
+// and gamma.
+__global__ __launch_bounds__(256) void inv_bwd_stats_kernel(const float* __restrict__ dx, const float* __restrict__ dr,
+                                                            const float* __restrict__ z, const float* __restrict__ u,
+                                                            const float* __restrict__ beta,
+                                                            const float* __restrict__ mean,
+                                                            const float* __restrict__ var,
+                                                            const float* __restrict__ gamma,
+                                                            const float* __restrict__ mu, int32_t k, int32_t l,
+                                                            float* __restrict__ p1, float* __restrict__ p2) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
+  const float drk = dr[(size_t)c * l + f] / (float)k;
+  const size_t base = (size_t)c * k * l + f;
+  float s1 = 0.f, s2 = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+    const float y = zh * g + sh;
+    const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
+    s1 += dy;
+    s2 += dy * zh;
+  }
+  p1[(size_t)c * l + f] = s1;
+  p2[(size_t)c * l + f] = s2;
+}
+
+// o1[f] = sum_c p1[c][f] and o2[f] = sum_c p2[c][f] (o2 may be null), in
+// colouring order
+__global__ __launch_bounds__(256) void inv_colsum_kernel(const float* __restrict__ p1, const float* __restrict__ p2,
+                                                         int32_t B, int32_t l, float* __restrict__ o1,
+                                                         float* __restrict__ o2) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  float s1 = 0.f, s2 = 0.f;
+  for (int c = 0; c < B; ++c) {
+    s1 += p1[(size_t)c * l + f];
+    if (p2) s2 += p2[(size_t)c * l + f];
+  }
+  o1[f] = s1;
+  if (o2) o2[f] = s2;
+}
+
+// Pass 2: dZ = gamma (N dY - sum dY - zhat sum dY zhat) / (N sqrt(var + eps))
+// in BF16 for the products below, and per colouring dU[c][f] = sum_i dZ (BF16
+// for the Gamma products, FP32 partial for the bias gradient).
+__global__ __launch_bounds__(256) void inv_bwd_apply_kernel(const float* __restrict__ dx, const float* __restrict__ dr,
+                                                            const float* __restrict__ z, const float* __restrict__ u,
+                                                            const float* __restrict__ beta,
+                                                            const float* __restrict__ mean,
+                                                            const float* __restrict__ var,
+                                                            const float* __restrict__ gamma,
+                                                            const float* __restrict__ mu,
+                                                            const float* __restrict__ dmu,
+                                                            const float* __restrict__ dgamma, int32_t B, int32_t k,
+                                                            int32_t l, uint16_t* __restrict__ dzb,
+                                                            uint16_t* __restrict__ dub, float* __restrict__ pdu) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
+  const float drk = dr[(size_t)c * l + f] / (float)k;
+  const float N = (float)B * (float)k, s1 = dmu[f], s2 = dgamma[f];
+  const float scale = g * rs / N;
+  const size_t base = (size_t)c * k * l + f;
+  float du = 0.f;
+  for (int i = 0; i < k; ++i) {
+    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+    const float y = zh * g + sh;
+    const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
+    const float v = scale * (N * dy - s1 - zh * s2);
+    dzb[base + (size_t)i * l] = to_bf16(v);
+    du += v;
+  }
+  dub[(size_t)c * l + f] = to_bf16(du);
+  pdu[(size_t)c * l + f] = du;
+}
+
+__global__ __launch_bounds__(256) void inv_adam_kernel(float* __restrict__ P, float* __restrict__ m,
+                                                       float* __restrict__ v, const float* __restrict__ g, int64_t total,
+                                                       float lr, float bc1, float bc2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const float gg = g[e];
+  const float mm = 0.9f * m[e] + 0.1f * gg;
+  const float vv = 0.999f * v[e] + 0.001f * gg * gg;
+  m[e] = mm;
+  v[e] = vv;
+  P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+}
+
+__global__ __launch_bounds__(256) void inv_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                          int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = to_bf16(src[e]);
+}
+
+}  // namespace dlm
+
+using namespace dlm;
+
+struct dlm_invnet {
+  int n = 0, k = 0, nl = 0, max_batch = 0, device = 0;
+  std::vector<int> lin, lout;
+  // packed FP32 trainables per layer: L, G, beta, then gamma, mu (hidden layers)
+  std::vector<int64_t> oL, oG, ob, og, om, oLb, oGb, orm, orv;
+  int64_t total = 0, nbf = 0, nrun = 0;
+  float *P = nullptr, *M = nullptr, *V = nullptr, *Gr = nullptr, *run = nullptr;
+  uint16_t* Pb = nullptr;  // BF16 copies of every L and G
+  // activations for max_batch colourings
+  std::vector<uint16_t*> X;  // X[j]: BF16 [N][lin[j]]
+  std::vector<uint16_t*> R;  // R[j]: BF16 [B][lin[j]]
+  std::vector<float*> Z;     // Z[j]: FP32 [N][lout[j]], X Lambda before bias and normalisation
+  std::vector<float*> U;     // U[j]: FP32 [B][lout[j]], R Gamma
+  std::vector<float*> mean, var;  // the batch statistics of the last training forward
+  float *dX = nullptr, *dR = nullptr, *df = nullptr, *fout = nullptr;
+  float *pa = nullptr, *pb = nullptr;  // per-colouring partial sums [B][lmax]
+  uint16_t *dZb = nullptr, *dUb = nullptr;
+  int adam_t = 0;
+  void* ws = nullptr;
+  rocblas_handle h = nullptr;
+};
+
+namespace {
+
+int gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A, int lda,
+         const void* B, int ldb, float beta, float* C, int ldc) {
+  const float alpha = 1.f;
+  const rocblas_status st =
+      rocblas_gemm_ex(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r, ldb,
+                      &beta, C, rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
+                      rocblas_gemm_algo_standard, 0, 0);
+  if (st != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_gemm_ex failed (%d)", (int)st);
+  return DLM_OK;
+}
+
+// row-major C[rows][cols] = A[rows][inner] W[inner][cols]  (column-major: C^T = W^T A^T)
+int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, int rows, int inner, int cols, float* C) {
+  return gemm(s, rocblas_operation_none, rocblas_operation_none, cols, rows, inner, W, cols, A, inner, 0.f, C, cols);
+}
+// row-major C[inner][cols] = A[rows][inner]^T D[rows][cols]
+int mm_at(dlm_invnet* s, const uint16_t* A, const uint16_t* D, int rows, int inner, int cols, float* C) {
+  return gemm(s, rocblas_operation_none, rocblas_operation_transpose, cols, inner, rows, D, cols, A, inner, 0.f, C,
+              cols);
+}
+// row-major C[rows][inner] = D[rows][cols] W[inner][cols]^T
+int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inner, int cols, float* C) {
+  return gemm(s, rocblas_operation_transpose, rocblas_operation_none, inner, rows, cols, W, cols, D, cols, 0.f, C,
+              inner);
+}
+
+unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+// forward of a batch of B colourings; train: BN from the batch statistics
+// (and, with update, the running estimates moved), else from the running
+// estimates
+int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool update, hipStream_t st) {
+  const int k = s->k;
+  const int64_t N = (int64_t)B * k;
+  hipLaunchKernelGGL(inv_onehot_kernel, dim3((unsigned)N), dim3(256), 0, st, colors, s->n, k, s->X[0]);
+  for (int j = 0; j < s->nl; ++j) {
+    const int li = s->lin[j], lo = s->lout[j];
+    if (j == 0)  // deeper class means come with the layer below's activation
+      hipLaunchKernelGGL(inv_class_mean_kernel, dim3((unsigned)((li + 255) / 256), (unsigned)B), dim3(256), 0, st,
+                         s->X[0], k, li, s->R[0]);
+    int rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
+    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
+    if (rc != DLM_OK) return rc;
+    if (j == s->nl - 1) {
+      hipLaunchKernelGGL(inv_output_kernel, dim3(blocks(B)), dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], k, B,
+                         s->fout);
+      break;
+    }
+    const dim3 tiles((unsigned)((lo + 255) / 256), (unsigned)B);
+    const float* mean = s->run + s->orm[j];
+    const float* var = s->run + s->orv[j];
+    if (train) {
+      hipLaunchKernelGGL(inv_fwd_stats_kernel, tiles, dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], k, lo,
+                         s->pa, s->pb);
+      hipLaunchKernelGGL(inv_fwd_stats_final_kernel, dim3(blocks(lo)), dim3(256), 0, st, s->pa, s->pb, B, k, lo,
+                         s->mean[j], s->var[j], s->run + s->orm[j], s->run + s->orv[j], update ? 1 : 0);
+      mean = s->mean[j];
+      var = s->var[j];
+    }
+    hipLaunchKernelGGL(inv_fwd_apply_kernel, tiles, dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], mean, var,
+                       s->P + s->og[j], s->P + s->om[j], k, lo, s->X[j + 1], s->R[j + 1]);
+  }
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+// gradients of the batch MSE into s->Gr (after a training forward)
+int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStream_t st) {
+  const int k = s->k;
+  const int64_t N = (int64_t)B * k;
+  hipLaunchKernelGGL(inv_mse_kernel, dim3(1), dim3(256), 0, st, s->fout, targets, B, s->df, loss);
+  const int jo = s->nl - 1;
+  hipLaunchKernelGGL(inv_out_bwd_kernel, dim3(blocks(N)), dim3(256), 0, st, s->df, k, B, s->dZb, s->dUb,
+                     s->Gr + s->ob[jo]);
+  for (int j = jo; j >= 0; --j) {
+    const int li = s->lin[j], lo = s->lout[j];
+    int rc = mm_at(s, s->X[j], s->dZb, (int)N, li, lo, s->Gr + s->oL[j]);
+    if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
+    if (rc != DLM_OK) return rc;
+    if (j == 0) break;
+    rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], (int)N, li, lo, s->dX);
+    if (rc == DLM_OK) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
+    if (rc != DLM_OK) return rc;
+    // through LReLU and the normalisation of layer j - 1 (width li)
+    const int p = j - 1;
+    const dim3 tiles((unsigned)((li + 255) / 256), (unsigned)B);
+    float* dmu = s->Gr + s->om[p];
+    float* dgamma = s->Gr + s->og[p];
+    hipLaunchKernelGGL(inv_bwd_stats_kernel, tiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
+                       s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], k, li, s->pa, s->pb);
+    hipLaunchKernelGGL(inv_colsum_kernel, dim3(blocks(li)), dim3(256), 0, st, s->pa, s->pb, B, li, dmu, dgamma);
+    hipLaunchKernelGGL(inv_bwd_apply_kernel, tiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
+                       s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], dmu, dgamma, B, k,
+                       li, s->dZb, s->dUb, s->pa);
+    hipLaunchKernelGGL(inv_colsum_kernel, dim3(blocks(li)), dim3(256), 0, st, s->pa, (const float*)nullptr, B, li,
+                       s->Gr + s->ob[p], (float*)nullptr);
+  }
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int inv_refresh_bf16(dlm_invnet* s, hipStream_t st) {
+  for (int j = 0; j < s->nl; ++j) {
+    const int64_t c = (int64_t)s->lin[j] * s->lout[j];
+    hipLaunchKernelGGL(inv_to_bf16_kernel, dim3(blocks(c)), dim3(256), 0, st, s->P + s->oL[j], s->Pb + s->oLb[j], c);
+    hipLaunchKernelGGL(inv_to_bf16_kernel, dim3(blocks(c)), dim3(256), 0, st, s->P + s->oG[j], s->Pb + s->oGb[j], c);
+  }
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int set_stream(dlm_invnet* s, hipStream_t st) {
+  if (rocblas_set_stream(s->h, st) != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_set_stream failed");
+  return DLM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, const float* params_host,
+                      int32_t max_batch, dlm_invnet** out) {
+  if (!out || !widths || !params_host) return set_error(DLM_E_INVAL, "dlm_invnet_create: null argument");
+  *out = nullptr;
+  if (n < 1 || n > 32767 || k < 2 || k > 32767 || nl < 1 || nl > 64 || max_batch < 1 || max_batch > 65536)
+    return set_error(DLM_E_INVAL, "dlm_invnet_create: n=%d k=%d layers=%d max_batch=%d", n, k, nl, max_batch);
+  if (widths[nl - 1] != 1) return set_error(DLM_E_INVAL, "dlm_invnet_create: the last layer must have width 1");
+  for (int j = 0; j < nl; ++j)
+    if (widths[j] < 1 || widths[j] > 65536) return set_error(DLM_E_INVAL, "dlm_invnet_create: width %d", widths[j]);
+  if ((int64_t)max_batch * k > 0x7fffffffll / 65536)
+    return set_error(DLM_E_INVAL, "dlm_invnet_create: max_batch * k too large");
+  dlm_invnet* s = new dlm_invnet();
+  s->n = n;
+  s->k = k;
+  s->nl = nl;
+  s->max_batch = max_batch;
+  DLM_HIP(hipGetDevice(&s->device));
+  int64_t o = 0, ob16 = 0, orun = 0, lmax = n;
+  for (int j = 0; j < nl; ++j) {
+    const int li = j ? widths[j - 1] : n, lo = widths[j];
+    s->lin.push_back(li);
+    s->lout.push_back(lo);
+    lmax = lmax > lo ? lmax : lo;
+    s->oL.push_back(o);
+    o += (int64_t)li * lo;
+    s->oG.push_back(o);
+    o += (int64_t)li * lo;
+    s->ob.push_back(o);
+    o += lo;
+    s->oLb.push_back(ob16);
+    ob16 += (int64_t)li * lo;
+    s->oGb.push_back(ob16);
+    ob16 += (int64_t)li * lo;
+    if (j < nl - 1) {
+      s->og.push_back(o);
+      o += lo;
+      s->om.push_back(o);
+      o += lo;
+      s->orm.push_back(orun);
+      orun += lo;
+      s->orv.push_back(orun);
+      orun += lo;
+    } else {
+      s->og.push_back(-1);
+      s->om.push_back(-1);
+      s->orm.push_back(-1);
+      s->orv.push_back(-1);
+    }
+  }
+  s->total = o;
+  s->nbf = ob16;
+  s->nrun = orun;
+  const int64_t B = max_batch, N = B * k;
+  // one allocation: P, M, V, Gr, run (FP32), Pb (BF16), activations, backward buffers
+  std::vector<std::pair<void**, int64_t>> parts;
+  parts.push_back({(void**)&s->P, 4 * o});
+  parts.push_back({(void**)&s->M, 4 * o});
+  parts.push_back({(void**)&s->V, 4 * o});
+  parts.push_back({(void**)&s->Gr, 4 * o});
+  parts.push_back({(void**)&s->run, 4 * std::max<int64_t>(orun, 1)});
+  parts.push_back({(void**)&s->Pb, 2 * ob16});
+  s->X.assign(nl, nullptr);
+  s->R.assign(nl, nullptr);
+  s->Z.assign(nl, nullptr);
+  s->U.assign(nl, nullptr);
+  s->mean.assign(nl, nullptr);
+  s->var.assign(nl, nullptr);
+  for (int j = 0; j < nl; ++j) {
+    parts.push_back({(void**)&s->X[j], 2 * N * s->lin[j]});
+    parts.push_back({(void**)&s->R[j], 2 * B * s->lin[j]});
+    parts.push_back({(void**)&s->Z[j], 4 * N * s->lout[j]});
+    parts.push_back({(void**)&s->U[j], 4 * B * s->lout[j]});
+    parts.push_back({(void**)&s->mean[j], 4 * s->lout[j]});
+    parts.push_back({(void**)&s->var[j], 4 * s->lout[j]});
+  }
+  parts.push_back({(void**)&s->dX, 4 * N * lmax});
+  parts.push_back({(void**)&s->pa, 4 * B * lmax});
+  parts.push_back({(void**)&s->pb, 4 * B * lmax});
+  parts.push_back({(void**)&s->dR, 4 * B * lmax});
+  parts.push_back({(void**)&s->df, 4 * B});
+  parts.push_back({(void**)&s->fout, 4 * B});
+  parts.push_back({(void**)&s->dZb, 2 * N * lmax});
+  parts.push_back({(void**)&s->dUb, 2 * B * lmax});
+  int64_t bytes = 0;
+  for (auto& p : parts) bytes += (p.second + 255) & ~255ll;
+  hipError_t e = hipMalloc(&s->ws, (size_t)bytes);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipMalloc (invnet)");
+  }
+  int64_t off = 0;
+  for (auto& p : parts) {
+    *p.first = (unsigned char*)s->ws + off;
+    off += (p.second + 255) & ~255ll;
+  }
+  if (rocblas_create_handle(&s->h) != rocblas_status_success) {
+    (void)hipFree(s->ws);
+    delete s;
+    return set_error(DLM_E_HIP, "rocblas_create_handle failed");
+  }
+  // host parameters: the trainables, then the running estimates
+  int rc = DLM_OK;
+  if (hipMemcpy(s->P, params_host, 4 * o, hipMemcpyHostToDevice) != hipSuccess ||
+      (orun && hipMemcpy(s->run, params_host + o, 4 * orun, hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemset(s->M, 0, 4 * o) != hipSuccess || hipMemset(s->V, 0, 4 * o) != hipSuccess)
+    rc = set_error(DLM_E_HIP, "dlm_invnet_create: upload failed");
+  if (rc == DLM_OK) rc = inv_refresh_bf16(s, nullptr);
+  if (rc == DLM_OK && hipDeviceSynchronize() != hipSuccess) rc = set_error(DLM_E_HIP, "dlm_invnet_create: sync");
+  if (rc != DLM_OK) {
+    rocblas_destroy_handle(s->h);
+    (void)hipFree(s->ws);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return DLM_OK;
+}
+
+int dlm_invnet_destroy(dlm_invnet* s) {
+  if (!s) return DLM_OK;
+  rocblas_destroy_handle(s->h);
+  (void)hipFree(s->ws);
+  delete s;
+  return DLM_OK;
+}
+
+int dlm_invnet_num_params(const dlm_invnet* s, int64_t* trainable, int64_t* running) {
+  if (!s || !trainable || !running) return set_error(DLM_E_INVAL, "dlm_invnet_num_params: null argument");
+  *trainable = s->total;
+  *running = s->nrun;
+  return DLM_OK;
+}
+
+int dlm_invnet_get_params(const dlm_invnet* s, float* params_dev, void* stream) {
+  if (!s || !params_dev) return set_error(DLM_E_INVAL, "dlm_invnet_get_params: null argument");
+  hipStream_t st = (hipStream_t)stream;
+  DLM_HIP(hipMemcpyAsync(params_dev, s->P, 4 * s->total, hipMemcpyDeviceToDevice, st));
+  if (s->nrun) DLM_HIP(hipMemcpyAsync(params_dev + s->total, s->run, 4 * s->nrun, hipMemcpyDeviceToDevice, st));
+  return DLM_OK;
+}
+
+int dlm_invnet_forward(dlm_invnet* s, const int16_t* colors, int32_t count, float* out, void* stream) {
+  if (!s || count < 0 || (count > 0 && (!colors || !out))) return set_error(DLM_E_INVAL, "dlm_invnet_forward: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = set_stream(s, st);
+  for (int32_t c0 = 0; rc == DLM_OK && c0 < count; c0 += s->max_batch) {
+    const int B = std::min(s->max_batch, count - c0);
+    rc = inv_forward(s, colors + (size_t)c0 * s->n, B, false, false, st);
+    if (rc == DLM_OK) DLM_HIP(hipMemcpyAsync(out + c0, s->fout, 4 * (size_t)B, hipMemcpyDeviceToDevice, st));
+  }
+  return rc;
+}
+
+int dlm_invnet_grad(dlm_invnet* s, const int16_t* colors, const float* targets, int32_t count, float* grad,
+                    float* loss, void* stream) {
+  if (!s || count < 1 || count > s->max_batch || !colors || !targets)
+    return set_error(DLM_E_INVAL, "dlm_invnet_grad: count=%d (need 1..max_batch) or null buffer", count);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = set_stream(s, st);
+  if (rc == DLM_OK) rc = inv_forward(s, colors, count, true, false, st);
+  if (rc == DLM_OK) rc = inv_backward(s, targets, count, loss, st);
+  if (rc == DLM_OK && grad) DLM_HIP(hipMemcpyAsync(grad, s->Gr, 4 * s->total, hipMemcpyDeviceToDevice, st));
+  return rc;
+}
+
+int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets, int32_t count, int32_t batch,
+                     int32_t epochs, float lr, float* losses, void* stream) {
+  if (!s || count < 0 || batch < 1 || batch > s->max_batch || epochs < 0 || !(lr > 0.f))
+    return set_error(DLM_E_INVAL, "dlm_invnet_train: count=%d batch=%d epochs=%d", count, batch, epochs);
+  if (count > 0 && (!colors || !targets)) return set_error(DLM_E_INVAL, "dlm_invnet_train: null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = set_stream(s, st);
+  int step = 0;
+  for (int ep = 0; rc == DLM_OK && ep < epochs; ++ep)
+    for (int32_t c0 = 0; rc == DLM_OK && c0 < count; c0 += batch) {
+      const int B = std::min(batch, count - c0);
+      rc = inv_forward(s, colors + (size_t)c0 * s->n, B, true, true, st);
+      if (rc == DLM_OK) rc = inv_backward(s, targets + c0, B, losses ? losses + step : nullptr, st);
+      if (rc != DLM_OK) break;
+      ++s->adam_t;
+      const float bc1 = 1.f - powf(0.9f, (float)s->adam_t), bc2 = 1.f - powf(0.999f, (float)s->adam_t);
+      hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks(s->total)), dim3(256), 0, st, s->P, s->M, s->V, s->Gr, s->total,
+                         lr, bc1, bc2);
+      rc = inv_refresh_bf16(s, st);
+      ++step;
+    }
+  return rc;
+}
+
+}  // extern "C"

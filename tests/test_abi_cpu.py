@@ -98,3 +98,26 @@ def test_diversity_argument_checks(L):
     # empty requests are no-ops
     assert L.dlm_partition_distance(10, 3, None, 0, None, 0, 0, None, 0, None, None) == 0
     assert L.dlm_nearest(None, 1, 0, 0, None, None) == 0
+
+
+def test_invnet_argument_checks(L):
+    """The colour-invariant network rejects bad shapes before any device work."""
+    from paper_2109_05948_amd import _abi
+    w = np.array([8, 4, 1], np.int32)
+    flat = np.zeros(1, np.float32)
+    h = C.c_void_p()
+    # k below 2, n of 0, a last width other than 1, a zero width, no widths
+    assert L.dlm_invnet_create(10, 1, 3, _abi._ptr(w), _abi._ptr(flat), 4, C.byref(h)) == -1
+    assert L.dlm_invnet_create(0, 3, 3, _abi._ptr(w), _abi._ptr(flat), 4, C.byref(h)) == -1
+    assert L.dlm_invnet_create(10, 3, 2, _abi._ptr(w), _abi._ptr(flat), 4, C.byref(h)) == -1
+    bad = np.array([8, 0, 1], np.int32)
+    assert L.dlm_invnet_create(10, 3, 3, _abi._ptr(bad), _abi._ptr(flat), 4, C.byref(h)) == -1
+    assert L.dlm_invnet_create(10, 3, 3, None, _abi._ptr(flat), 4, C.byref(h)) == -1
+    assert L.dlm_invnet_create(10, 3, 3, _abi._ptr(w), _abi._ptr(flat), 0, C.byref(h)) == -1
+    assert h.value is None
+    # calls on no network
+    assert L.dlm_invnet_forward(None, None, 1, None, None) == -1
+    assert L.dlm_invnet_grad(None, None, None, 1, None, None, None) == -1
+    assert L.dlm_invnet_train(None, None, None, 1, 1, 1, C.c_float(1e-3), None, None) == -1
+    assert L.dlm_invnet_get_params(None, None, None) == -1
+    assert L.dlm_invnet_destroy(None) == 0
