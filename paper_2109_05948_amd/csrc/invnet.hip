@@ -52,57 +52,125 @@ __global__ __launch_bounds__(256) void inv_class_mean_kernel(const uint16_t* __r
   r[(size_t)c * l + f] = to_bf16(s / (float)k);
 }
 
-// Forward normalisation statistics, per (colouring c, feature f): over the k
-// class rows of v = z + u[c] + beta, the mean and the sum of squared
-// deviations (two passes; the second re-reads the block's rows from cache).
+// Per-colouring kernels: a block of four waves covers 64 features of one
+// colouring c; wave w takes the class rows i = w, w + 4, ... and the four
+// partial sums are combined in wave order through LDS.
+constexpr int kTileF = 64;
+
+__device__ __forceinline__ float sum4(float (*sh)[kTileF], int lane) {
+  return (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+}
+
+// Forward normalisation statistics of colouring c over its k class rows of
+// v = z + u[c] + beta: the mean and the sum of squared deviations (two
+// passes; the second re-reads the block's rows from cache).
 __global__ __launch_bounds__(256) void inv_fwd_stats_kernel(const float* __restrict__ z, const float* __restrict__ u,
                                                             const float* __restrict__ beta, int32_t k, int32_t l,
                                                             float* __restrict__ pmean, float* __restrict__ pm2) {
-  const int c = blockIdx.y;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
-  const float add = u[(size_t)c * l + f] + beta[f];
+  __shared__ float sh[4][kTileF];
+  const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
+  const float add = ok ? u[(size_t)c * l + f] + beta[f] : 0.f;
   const float* zc = z + (size_t)c * k * l + f;
   float s = 0.f;
-  for (int i = 0; i < k; ++i) s += zc[(size_t)i * l];
-  const float m = s / (float)k + add;
+  if (ok)
+#pragma unroll 4
+    for (int i = w; i < k; i += 4) s += zc[(size_t)i * l];
+  sh[w][lane] = s;
+  __syncthreads();
+  const float m = sum4(sh, lane) / (float)k + add;
   float q = 0.f;
-  for (int i = 0; i < k; ++i) {
-    const float d = zc[(size_t)i * l] + add - m;
-    q += d * d;
+  if (ok)
+#pragma unroll 4
+    for (int i = w; i < k; i += 4) {
+      const float d = zc[(size_t)i * l] + add - m;
+      q += d * d;
+    }
+  __syncthreads();
+  sh[w][lane] = q;
+  __syncthreads();
+  if (w == 0 && ok) {
+    pmean[(size_t)c * l + f] = m;
+    pm2[(size_t)c * l + f] = sum4(sh, lane);
   }
-  pmean[(size_t)c * l + f] = m;
-  pm2[(size_t)c * l + f] = q;
 }
 
-// The B groups of k rows merged in colouring order (equal group sizes):
-// mean = average of the group means, M2 = sum of the group M2 plus
-// k sum (group mean - mean)^2; biased variance M2 / (B k).  With update, the
-// running estimates move by the momentum towards (mean, unbiased variance).
-__global__ __launch_bounds__(256) void inv_fwd_stats_final_kernel(const float* __restrict__ pmean,
-                                                                  const float* __restrict__ pm2, int32_t B,
-                                                                  int32_t k, int32_t l, float* __restrict__ mean,
-                                                                  float* __restrict__ var, float* __restrict__ rm,
-                                                                  float* __restrict__ rv, int32_t update) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
+// Column reductions over the B colourings: a block of 16 waves covers 64
+// features; wave w sums the colourings of the w-th of 16 contiguous slices
+// in order, and the slices are combined in order.
+constexpr int kColWaves = 16;
+
+__device__ __forceinline__ float col_slice_sum(const float* __restrict__ p, int B, int l, int f, int w) {
+  const int c0 = (int)((int64_t)B * w / kColWaves), c1 = (int)((int64_t)B * (w + 1) / kColWaves);
   float s = 0.f;
-  for (int c = 0; c < B; ++c) s += pmean[(size_t)c * l + f];
-  const float m = s / (float)B;
+#pragma unroll 4
+  for (int c = c0; c < c1; ++c) s += p[(size_t)c * l + f];
+  return s;
+}
+
+__device__ __forceinline__ float col_combine(float (*sh)[kTileF], int lane) {
+  float t = 0.f;
+  for (int w = 0; w < kColWaves; ++w) t += sh[w][lane];
+  return t;
+}
+
+// The B groups of k rows merged (equal group sizes): mean = average of the
+// group means, M2 = sum of the group M2 plus k sum (group mean - mean)^2;
+// biased variance M2 / (B k).  With update, the running estimates move by
+// the momentum towards (mean, unbiased variance).
+__global__ __launch_bounds__(1024) void inv_fwd_stats_final_kernel(const float* __restrict__ pmean,
+                                                                   const float* __restrict__ pm2, int32_t B,
+                                                                   int32_t k, int32_t l, float* __restrict__ mean,
+                                                                   float* __restrict__ var, float* __restrict__ rm,
+                                                                   float* __restrict__ rv, int32_t update) {
+  __shared__ float sh[kColWaves][kTileF];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
+  sh[w][lane] = ok ? col_slice_sum(pmean, B, l, f, w) : 0.f;
+  __syncthreads();
+  const float m = col_combine(sh, lane) / (float)B;
   float q = 0.f, d2 = 0.f;
-  for (int c = 0; c < B; ++c) {
-    const float d = pmean[(size_t)c * l + f] - m;
-    q += pm2[(size_t)c * l + f];
-    d2 += d * d;
+  if (ok) {
+    const int c0 = (int)((int64_t)B * w / kColWaves), c1 = (int)((int64_t)B * (w + 1) / kColWaves);
+    for (int c = c0; c < c1; ++c) {
+      const float d = pmean[(size_t)c * l + f] - m;
+      q += pm2[(size_t)c * l + f];
+      d2 += d * d;
+    }
   }
-  const float N = (float)B * (float)k;
-  const float v = (q + (float)k * d2) / N;
-  mean[f] = m;
-  var[f] = v;
-  if (update) {
-    rm[f] = (1.f - kBnMomentum) * rm[f] + kBnMomentum * m;
-    rv[f] = (1.f - kBnMomentum) * rv[f] + kBnMomentum * v * (N / (N - 1.f));
+  __syncthreads();
+  sh[w][lane] = q + (float)k * d2;
+  __syncthreads();
+  if (w == 0 && ok) {
+    const float N = (float)B * (float)k;
+    const float v = col_combine(sh, lane) / N;
+    mean[f] = m;
+    var[f] = v;
+    if (update) {
+      rm[f] = (1.f - kBnMomentum) * rm[f] + kBnMomentum * m;
+      rv[f] = (1.f - kBnMomentum) * rv[f] + kBnMomentum * v * (N / (N - 1.f));
+    }
   }
+}
+
+// o1[f] = sum_c p1[c][f] and o2[f] = sum_c p2[c][f] (o2 may be null)
+__global__ __launch_bounds__(1024) void inv_colsum_kernel(const float* __restrict__ p1, const float* __restrict__ p2,
+                                                          int32_t B, int32_t l, float* __restrict__ o1,
+                                                          float* __restrict__ o2) {
+  __shared__ float sh[kColWaves][kTileF];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
+  sh[w][lane] = ok ? col_slice_sum(p1, B, l, f, w) : 0.f;
+  __syncthreads();
+  if (w == 0 && ok) o1[f] = col_combine(sh, lane);
+  if (!p2) return;  // uniform over the block
+  __syncthreads();
+  sh[w][lane] = ok ? col_slice_sum(p2, B, l, f, w) : 0.f;
+  __syncthreads();
+  if (w == 0 && ok) o2[f] = col_combine(sh, lane);
 }
 
 // Normalise, scale, shift and activate the k class rows of colouring c:
@@ -115,69 +183,125 @@ __global__ __launch_bounds__(256) void inv_fwd_apply_kernel(const float* __restr
                                                             const float* __restrict__ gamma,
                                                             const float* __restrict__ mu, int32_t k, int32_t l,
                                                             uint16_t* __restrict__ xn, uint16_t* __restrict__ rn) {
-  const int c = blockIdx.y;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
-  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
-  const size_t base = (size_t)c * k * l + f;
+  __shared__ float sh[4][kTileF];
+  const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
   float r = 0.f;
-  for (int i = 0; i < k; ++i) {
-    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-    const float y = zh * g + sh;
-    const uint16_t xb = to_bf16(y > 0.f ? y : kInvSlope * y);
-    xn[base + (size_t)i * l] = xb;
-    r += from_bf16(xb);
+  if (ok) {
+    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh_ = mu[f];
+    const size_t base = (size_t)c * k * l + f;
+#pragma unroll 4
+    for (int i = w; i < k; i += 4) {
+      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+      const float y = zh * g + sh_;
+      const uint16_t xb = to_bf16(y > 0.f ? y : kInvSlope * y);
+      xn[base + (size_t)i * l] = xb;
+      r += from_bf16(xb);
+    }
   }
-  rn[(size_t)c * l + f] = to_bf16(r / (float)k);
+  sh[w][lane] = r;
+  __syncthreads();
+  if (w == 0 && ok) rn[(size_t)c * l + f] = to_bf16(sum4(sh, lane) / (float)k);
 }
 
-// output layer: f[c] = mean_i z[c k + i] + u[c] + beta
-__global__ __launch_bounds__(256) void inv_output_kernel(const float* __restrict__ z, const float* __restrict__ u,
-                                                         const float* __restrict__ beta, int32_t k, int32_t B,
-                                                         float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= B) return;
-  float s = 0.f;
-  for (int i = 0; i < k; ++i) s += z[(size_t)c * k + i];
-  out[c] = s / (float)k + u[c] + beta[0];
+// Output layer (width 1), one block per colouring c: z_i = X[c k + i] . lambda
+// for the k class rows (four waves, rows split round-robin, lanes over the
+// features), u = R[c] . gamma, and f[c] = (1/k) sum_i z_i + u + beta.  The
+// weights are the FP32 trainables; sums run in a fixed order.
+__global__ __launch_bounds__(256) void inv_out_fwd_kernel(const uint16_t* __restrict__ x,
+                                                          const uint16_t* __restrict__ r,
+                                                          const float* __restrict__ lam,
+                                                          const float* __restrict__ gam,
+                                                          const float* __restrict__ beta, int32_t k, int32_t l,
+                                                          float* __restrict__ out) {
+  __shared__ float part[5];
+  const int c = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float acc = 0.f;
+  for (int i = w; i < k; i += 4) {
+    const uint16_t* row = x + ((size_t)c * k + i) * l;
+    float z = 0.f;
+    for (int f = lane; f < l; f += 64) z += from_bf16(row[f]) * lam[f];
+    acc += z;
+  }
+  float u = 0.f;
+  if (w == 0)
+    for (int f = lane; f < l; f += 64) u += from_bf16(r[(size_t)c * l + f]) * gam[f];
+  for (int o = 32; o > 0; o >>= 1) {
+    acc += __shfl_xor(acc, o);
+    u += __shfl_xor(u, o);
+  }
+  if (lane == 0) {
+    part[w] = acc;
+    if (w == 0) part[4] = u;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = (part[0] + part[1] + part[2] + part[3]) / (float)k + part[4] + beta[0];
 }
 
-// MSE on one batch: df[c] = 2 (f - t) / B, loss = mean (f - t)^2 (one block, fixed order)
+// MSE on one batch: df[c] = 2 (f - t) / B, loss = mean (f - t)^2, and the
+// output bias gradient sum_c df[c] (one block, fixed order)
 __global__ __launch_bounds__(256) void inv_mse_kernel(const float* __restrict__ f, const float* __restrict__ t,
-                                                      int32_t B, float* __restrict__ df, float* __restrict__ loss) {
-  __shared__ float part[256];
-  float s = 0.f;
+                                                      int32_t B, float* __restrict__ df, float* __restrict__ loss,
+                                                      float* __restrict__ dbeta) {
+  __shared__ float part[256], pd[256];
+  float s = 0.f, sd = 0.f;
   for (int c = threadIdx.x; c < B; c += 256) {
     const float d = f[c] - t[c];
     df[c] = 2.f * d / (float)B;
     s += d * d;
+    sd += 2.f * d / (float)B;
   }
   part[threadIdx.x] = s;
+  pd[threadIdx.x] = sd;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if (threadIdx.x < w) {
+      part[threadIdx.x] += part[threadIdx.x + w];
+      pd[threadIdx.x] += pd[threadIdx.x + w];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && loss) *loss = part[0] / (float)B;
+  if (threadIdx.x == 0) {
+    if (loss) *loss = part[0] / (float)B;
+    *dbeta = pd[0];
+  }
 }
 
-// output layer backward: dz (width 1) = df[c] / k on every class row, dU = df
-__global__ __launch_bounds__(256) void inv_out_bwd_kernel(const float* __restrict__ df, int32_t k, int32_t B,
-                                                          uint16_t* __restrict__ dzb, uint16_t* __restrict__ dub,
-                                                          float* __restrict__ dbeta) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (int64_t)B * k) dzb[e] = to_bf16(df[e / k] / (float)k);
-  if (e < B) dub[e] = to_bf16(df[e]);
-  if (e == 0) {
-    float s = 0.f;
-    for (int c = 0; c < B; ++c) s += df[c];
-    dbeta[0] = s;
-  }
+// Output layer weight gradients, per (colouring c, feature f): with
+// dz = df[c] / k on every class row and du = df[c],
+//   pa[c][f] = (df[c] / k) sum_i X[c k + i][f]   (summed over c: d lambda)
+//   pb[c][f] = df[c] R[c][f]                      (summed over c: d gamma)
+__global__ __launch_bounds__(256) void inv_out_grad_kernel(const uint16_t* __restrict__ x,
+                                                           const uint16_t* __restrict__ r,
+                                                           const float* __restrict__ df, int32_t k, int32_t l,
+                                                           float* __restrict__ pa, float* __restrict__ pb) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  float sx = 0.f;
+  for (int i = 0; i < k; ++i) sx += from_bf16(x[((size_t)c * k + i) * l + f]);
+  const float d = df[c];
+  pa[(size_t)c * l + f] = d / (float)k * sx;
+  pb[(size_t)c * l + f] = d * from_bf16(r[(size_t)c * l + f]);
+}
+
+// Output layer input gradients: dX[c k + i][f] = (df[c] / k) lambda[f] and
+// dR[c][f] = df[c] gamma[f]
+__global__ __launch_bounds__(256) void inv_out_dx_kernel(const float* __restrict__ df, const float* __restrict__ lam,
+                                                         const float* __restrict__ gam, int32_t k, int32_t l,
+                                                         float* __restrict__ dx, float* __restrict__ dr) {
+  const int c = blockIdx.y;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= l) return;
+  const float d = df[c], v = d / (float)k * lam[f];
+  for (int i = 0; i < k; ++i) dx[((size_t)c * k + i) * l + f] = v;
+  dr[(size_t)c * l + f] = d * gam[f];
 }
 
 // Backward through LReLU and the normalisation of a hidden layer, pass 1,
-// per (colouring c, feature f): with zhat recomputed from the stored z and
+// per colouring c: with zhat recomputed from the stored z and
 // dY = (dX + dR[c] / k) LReLU'(zhat gamma + mu) over the k class rows (the
 // dR / k term is the class-mean path of the layer above), the partial sums
 // of dY and dY zhat; summed over colourings these are the gradients of mu
@@ -190,39 +314,32 @@ __global__ __launch_bounds__(256) void inv_bwd_stats_kernel(const float* __restr
                                                             const float* __restrict__ gamma,
                                                             const float* __restrict__ mu, int32_t k, int32_t l,
                                                             float* __restrict__ p1, float* __restrict__ p2) {
-  const int c = blockIdx.y;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
-  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
-  const float drk = dr[(size_t)c * l + f] / (float)k;
-  const size_t base = (size_t)c * k * l + f;
+  __shared__ float sh1[4][kTileF], sh2[4][kTileF];
+  const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
   float s1 = 0.f, s2 = 0.f;
-  for (int i = 0; i < k; ++i) {
-    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-    const float y = zh * g + sh;
-    const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
-    s1 += dy;
-    s2 += dy * zh;
+  if (ok) {
+    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
+    const float drk = dr[(size_t)c * l + f] / (float)k;
+    const size_t base = (size_t)c * k * l + f;
+#pragma unroll 4
+    for (int i = w; i < k; i += 4) {
+      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+      const float y = zh * g + sh;
+      const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
+      s1 += dy;
+      s2 += dy * zh;
+    }
   }
-  p1[(size_t)c * l + f] = s1;
-  p2[(size_t)c * l + f] = s2;
-}
-
-// o1[f] = sum_c p1[c][f] and o2[f] = sum_c p2[c][f] (o2 may be null), in
-// colouring order
-__global__ __launch_bounds__(256) void inv_colsum_kernel(const float* __restrict__ p1, const float* __restrict__ p2,
-                                                         int32_t B, int32_t l, float* __restrict__ o1,
-                                                         float* __restrict__ o2) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
-  float s1 = 0.f, s2 = 0.f;
-  for (int c = 0; c < B; ++c) {
-    s1 += p1[(size_t)c * l + f];
-    if (p2) s2 += p2[(size_t)c * l + f];
+  sh1[w][lane] = s1;
+  sh2[w][lane] = s2;
+  __syncthreads();
+  if (w == 0 && ok) {
+    p1[(size_t)c * l + f] = sum4(sh1, lane);
+    p2[(size_t)c * l + f] = sum4(sh2, lane);
   }
-  o1[f] = s1;
-  if (o2) o2[f] = s2;
 }
 
 // Pass 2: dZ = gamma (N dY - sum dY - zhat sum dY zhat) / (N sqrt(var + eps))
@@ -239,31 +356,43 @@ __global__ __launch_bounds__(256) void inv_bwd_apply_kernel(const float* __restr
                                                             const float* __restrict__ dgamma, int32_t B, int32_t k,
                                                             int32_t l, uint16_t* __restrict__ dzb,
                                                             uint16_t* __restrict__ dub, float* __restrict__ pdu) {
-  const int c = blockIdx.y;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= l) return;
-  const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-  const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
-  const float drk = dr[(size_t)c * l + f] / (float)k;
-  const float N = (float)B * (float)k, s1 = dmu[f], s2 = dgamma[f];
-  const float scale = g * rs / N;
-  const size_t base = (size_t)c * k * l + f;
+  __shared__ float shu[4][kTileF];
+  const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int f = blockIdx.x * kTileF + lane;
+  const bool ok = f < l;
   float du = 0.f;
-  for (int i = 0; i < k; ++i) {
-    const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-    const float y = zh * g + sh;
-    const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
-    const float v = scale * (N * dy - s1 - zh * s2);
-    dzb[base + (size_t)i * l] = to_bf16(v);
-    du += v;
+  if (ok) {
+    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
+    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
+    const float drk = dr[(size_t)c * l + f] / (float)k;
+    const float N = (float)B * (float)k, s1 = dmu[f], s2 = dgamma[f];
+    const float scale = g * rs / N;
+    const size_t base = (size_t)c * k * l + f;
+#pragma unroll 4
+    for (int i = w; i < k; i += 4) {
+      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
+      const float y = zh * g + sh;
+      const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
+      const float v = scale * (N * dy - s1 - zh * s2);
+      dzb[base + (size_t)i * l] = to_bf16(v);
+      du += v;
+    }
   }
-  dub[(size_t)c * l + f] = to_bf16(du);
-  pdu[(size_t)c * l + f] = du;
+  shu[w][lane] = du;
+  __syncthreads();
+  if (w == 0 && ok) {
+    const float t = sum4(shu, lane);
+    dub[(size_t)c * l + f] = to_bf16(t);
+    pdu[(size_t)c * l + f] = t;
+  }
 }
 
+// Adam on one layer's trainables (Lambda, Gamma, beta[, gamma, mu], packed);
+// the first nb of them (Lambda and Gamma) also refresh their BF16 copy
 __global__ __launch_bounds__(256) void inv_adam_kernel(float* __restrict__ P, float* __restrict__ m,
                                                        float* __restrict__ v, const float* __restrict__ g, int64_t total,
-                                                       float lr, float bc1, float bc2) {
+                                                       float lr, float bc1, float bc2, uint16_t* __restrict__ pb,
+                                                       int64_t nb) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const float gg = g[e];
@@ -271,7 +400,9 @@ __global__ __launch_bounds__(256) void inv_adam_kernel(float* __restrict__ P, fl
   const float vv = 0.999f * v[e] + 0.001f * gg * gg;
   m[e] = mm;
   v[e] = vv;
-  P[e] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+  const float p = P[e] - lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+  P[e] = p;
+  if (e < nb) pb[e] = to_bf16(p);
 }
 
 __global__ __launch_bounds__(256) void inv_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
@@ -335,6 +466,7 @@ int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inn
 }
 
 unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
+unsigned col_blocks(int64_t l) { return (unsigned)((l + kTileF - 1) / kTileF); }
 
 // forward of a batch of B colourings; train: BN from the batch statistics
 // (and, with update, the running estimates moved), else from the running
@@ -348,21 +480,21 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
     if (j == 0)  // deeper class means come with the layer below's activation
       hipLaunchKernelGGL(inv_class_mean_kernel, dim3((unsigned)((li + 255) / 256), (unsigned)B), dim3(256), 0, st,
                          s->X[0], k, li, s->R[0]);
+    if (j == s->nl - 1) {  // width 1: matrix-vector products, no GEMM
+      hipLaunchKernelGGL(inv_out_fwd_kernel, dim3((unsigned)B), dim3(256), 0, st, s->X[j], s->R[j], s->P + s->oL[j],
+                         s->P + s->oG[j], s->P + s->ob[j], k, li, s->fout);
+      break;
+    }
     int rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
     if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
     if (rc != DLM_OK) return rc;
-    if (j == s->nl - 1) {
-      hipLaunchKernelGGL(inv_output_kernel, dim3(blocks(B)), dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], k, B,
-                         s->fout);
-      break;
-    }
-    const dim3 tiles((unsigned)((lo + 255) / 256), (unsigned)B);
+    const dim3 tiles((unsigned)((lo + kTileF - 1) / kTileF), (unsigned)B);
     const float* mean = s->run + s->orm[j];
     const float* var = s->run + s->orv[j];
     if (train) {
       hipLaunchKernelGGL(inv_fwd_stats_kernel, tiles, dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], k, lo,
                          s->pa, s->pb);
-      hipLaunchKernelGGL(inv_fwd_stats_final_kernel, dim3(blocks(lo)), dim3(256), 0, st, s->pa, s->pb, B, k, lo,
+      hipLaunchKernelGGL(inv_fwd_stats_final_kernel, dim3(col_blocks(lo)), dim3(1024), 0, st, s->pa, s->pb, B, k, lo,
                          s->mean[j], s->var[j], s->run + s->orm[j], s->run + s->orv[j], update ? 1 : 0);
       mean = s->mean[j];
       var = s->var[j];
@@ -378,31 +510,39 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
 int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStream_t st) {
   const int k = s->k;
   const int64_t N = (int64_t)B * k;
-  hipLaunchKernelGGL(inv_mse_kernel, dim3(1), dim3(256), 0, st, s->fout, targets, B, s->df, loss);
   const int jo = s->nl - 1;
-  hipLaunchKernelGGL(inv_out_bwd_kernel, dim3(blocks(N)), dim3(256), 0, st, s->df, k, B, s->dZb, s->dUb,
-                     s->Gr + s->ob[jo]);
+  hipLaunchKernelGGL(inv_mse_kernel, dim3(1), dim3(256), 0, st, s->fout, targets, B, s->df, loss, s->Gr + s->ob[jo]);
   for (int j = jo; j >= 0; --j) {
     const int li = s->lin[j], lo = s->lout[j];
-    int rc = mm_at(s, s->X[j], s->dZb, (int)N, li, lo, s->Gr + s->oL[j]);
-    if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
-    if (rc != DLM_OK) return rc;
-    if (j == 0) break;
-    rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], (int)N, li, lo, s->dX);
-    if (rc == DLM_OK) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
-    if (rc != DLM_OK) return rc;
+    const dim3 tiles((unsigned)((li + 255) / 256), (unsigned)B);
+    const dim3 ftiles((unsigned)((li + kTileF - 1) / kTileF), (unsigned)B);
+    if (j == jo) {  // width 1: no GEMM
+      hipLaunchKernelGGL(inv_out_grad_kernel, tiles, dim3(256), 0, st, s->X[j], s->R[j], s->df, k, li, s->pa, s->pb);
+      hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, s->pb, B, li,
+                         s->Gr + s->oL[j], s->Gr + s->oG[j]);
+      if (j == 0) break;
+      hipLaunchKernelGGL(inv_out_dx_kernel, tiles, dim3(256), 0, st, s->df, s->P + s->oL[j], s->P + s->oG[j], k, li,
+                         s->dX, s->dR);
+    } else {
+      int rc = mm_at(s, s->X[j], s->dZb, (int)N, li, lo, s->Gr + s->oL[j]);
+      if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
+      if (rc != DLM_OK) return rc;
+      if (j == 0) break;
+      rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], (int)N, li, lo, s->dX);
+      if (rc == DLM_OK) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
+      if (rc != DLM_OK) return rc;
+    }
     // through LReLU and the normalisation of layer j - 1 (width li)
     const int p = j - 1;
-    const dim3 tiles((unsigned)((li + 255) / 256), (unsigned)B);
     float* dmu = s->Gr + s->om[p];
     float* dgamma = s->Gr + s->og[p];
-    hipLaunchKernelGGL(inv_bwd_stats_kernel, tiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
+    hipLaunchKernelGGL(inv_bwd_stats_kernel, ftiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
                        s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], k, li, s->pa, s->pb);
-    hipLaunchKernelGGL(inv_colsum_kernel, dim3(blocks(li)), dim3(256), 0, st, s->pa, s->pb, B, li, dmu, dgamma);
-    hipLaunchKernelGGL(inv_bwd_apply_kernel, tiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
+    hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, s->pb, B, li, dmu, dgamma);
+    hipLaunchKernelGGL(inv_bwd_apply_kernel, ftiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
                        s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], dmu, dgamma, B, k,
                        li, s->dZb, s->dUb, s->pa);
-    hipLaunchKernelGGL(inv_colsum_kernel, dim3(blocks(li)), dim3(256), 0, st, s->pa, (const float*)nullptr, B, li,
+    hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, (const float*)nullptr, B, li,
                        s->Gr + s->ob[p], (float*)nullptr);
   }
   DLM_HIP(hipGetLastError());
@@ -609,9 +749,12 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets,
       if (rc != DLM_OK) break;
       ++s->adam_t;
       const float bc1 = 1.f - powf(0.9f, (float)s->adam_t), bc2 = 1.f - powf(0.999f, (float)s->adam_t);
-      hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks(s->total)), dim3(256), 0, st, s->P, s->M, s->V, s->Gr, s->total,
-                         lr, bc1, bc2);
-      rc = inv_refresh_bf16(s, st);
+      for (int j = 0; j < s->nl; ++j) {  // one layer's trainables are contiguous
+        const int64_t o = s->oL[j], cnt = (j + 1 < s->nl ? s->oL[j + 1] : s->total) - o;
+        hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks(cnt)), dim3(256), 0, st, s->P + o, s->M + o, s->V + o,
+                           s->Gr + o, cnt, lr, bc1, bc2, s->Pb + s->oLb[j], 2 * (int64_t)s->lin[j] * s->lout[j]);
+      }
+      DLM_HIP(hipGetLastError());
       ++step;
     }
   return rc;
