@@ -149,6 +149,11 @@ def main():
     ap.add_argument("--diversity", type=int, default=0,
                     help="memetic1000: K > 0 runs the loops with the paper's diversity steps (K nearest "
                          "neighbours, one child per individual, spacing update)")
+    ap.add_argument("--network", default="mlp", choices=["mlp", "invariant"],
+                    help="memetic1000: the learned loop's scorer (the per-class MLP, or the paper's "
+                         "colour-invariant network at its k-COL depth)")
+    ap.add_argument("--epochs", type=int, default=0,
+                    help="memetic1000: training epochs per generation (default: the workload's)")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
@@ -353,6 +358,7 @@ def bench_memetic(args, w, dlm, torch):
     value = the learned loop's median time over the seeds (a run that misses
     the cutoff counts as infinite; null if the median does)."""
     from paper_2109_05948_amd import memetic
+    from workloads.invnet_init import col_widths, invnet_weights
     from workloads.scorer_init import scorer_weights
     g, T = w.graphs[0], w.iters[0]
     k = args.k or w.k[0]
@@ -360,6 +366,13 @@ def bench_memetic(args, w, dlm, torch):
     e = w.extra
     pop = args.pop or w.pop
     seeds = [int(x) for x in args.seeds.split(",")]
+    epochs = args.epochs or e["epochs"]
+    if args.network == "invariant":  # the paper's network: its batch of 100
+        params = invnet_weights(g.n, col_widths(g.n), seed=0)
+        params["widths"] = col_widths(g.n)
+        batch = 100
+    else:
+        params, batch = scorer_weights(g.n, seed=0), e["batch"]
     res = {}
     for name in args.loops.split(","):
         runs = []
@@ -367,9 +380,9 @@ def bench_memetic(args, w, dlm, torch):
             log(f"memetic {name} k={k} seed={sd}")
             r = memetic.run(G, k, pop, T, learned=(name == "learned"), seed=sd,
                             cutoff_s=args.cutoff, children_per_pair=e["children_per_pair"],
-                            keep_frac=e["keep_frac"], scorer_params=scorer_weights(g.n, seed=0),
-                            batch=e["batch"], epochs=e["epochs"], lr=e["lr"], log=log,
-                            diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
+                            keep_frac=e["keep_frac"], scorer_params=params, batch=batch, epochs=epochs,
+                            lr=e["lr"], log=log, diversity=args.diversity > 0,
+                            neighbours=max(args.diversity, 1), network=args.network)
             runs.append({"seed": sd, "time_to_legal_s": r.time_to_legal, "best_f": r.best,
                          "generations": r.generations, "wall_s": r.wall,
                          "tabu_moves_per_s": r.tabu_moves / r.wall,
@@ -386,7 +399,8 @@ def bench_memetic(args, w, dlm, torch):
            "config": {"workload": "memetic1000", "graph": "G(n=1000, p=0.5) seed 0", "k": k,
                       "population": pop, "children_per_pair": e["children_per_pair"],
                       "keep_frac": e["keep_frac"], "iters_per_tabu": T, "cutoff_s": args.cutoff,
-                      "seeds": seeds, "diversity_neighbours": args.diversity},
+                      "seeds": seeds, "diversity_neighbours": args.diversity, "network": args.network,
+                      "train_batch": batch, "epochs": epochs},
            "loops": res}
     print(json.dumps(out), flush=True)
 

@@ -501,7 +501,8 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * in order; copied at creation.  max_batch bounds the colourings of one
  * training step and the chunk of one evaluation pass; the network allocates
  * its activations for that many (about 6 (max_batch k) sum(widths) + 6
- * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767.
+ * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767, max_batch <= 65535,
+ * max_batch k < 2^31.
  * ---------------------------------------------------------------------- */
 typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, rocBLAS handle */
 

@@ -430,6 +430,8 @@ class InvNet:
                                                               _stream(stream)))
         return out
 
+    score = forward  # the scorer interface of the memetic loop
+
     def grad(self, colors: torch.Tensor, targets: torch.Tensor, stream=None):
         """dlm_invnet_grad -> (flat FP32 gradient of the batch MSE, loss)."""
         _dev(colors, torch.int16, "colors")

@@ -52,47 +52,136 @@ __global__ __launch_bounds__(256) void inv_class_mean_kernel(const uint16_t* __r
   r[(size_t)c * l + f] = to_bf16(s / (float)k);
 }
 
-// Per-colouring kernels: a block of four waves covers 64 features of one
-// colouring c; wave w takes the class rows i = w, w + 4, ... and the four
-// partial sums are combined in wave order through LDS.
+// Per-colouring kernels: a block of four waves covers 64 V features of one
+// colouring c (V consecutive features per lane, V = 4, 2 or 1 as the layer
+// width allows aligned vector access); wave w takes the class rows
+// i = w, w + 4, ... and the four partial sums are combined in wave order
+// through LDS.
 constexpr int kTileF = 64;
 
-__device__ __forceinline__ float sum4(float (*sh)[kTileF], int lane) {
-  return (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+template <int V>
+struct vec {
+  float x[V];
+};
+
+template <int V>
+__device__ __forceinline__ vec<V> ldv(const float* __restrict__ p) {
+  vec<V> r;
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    r.x[0] = t.x, r.x[1] = t.y, r.x[2] = t.z, r.x[3] = t.w;
+  } else if constexpr (V == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    r.x[0] = t.x, r.x[1] = t.y;
+  } else {
+    r.x[0] = *p;
+  }
+  return r;
+}
+
+template <int V>
+__device__ __forceinline__ void stv(float* __restrict__ p, const vec<V>& v) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.x[0], v.x[1], v.x[2], v.x[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2*>(p) = make_float2(v.x[0], v.x[1]);
+  } else {
+    *p = v.x[0];
+  }
+}
+
+// BF16 store of V values; returns the rounded values
+template <int V>
+__device__ __forceinline__ vec<V> stv_bf16(uint16_t* __restrict__ p, const vec<V>& v) {
+  vec<V> r;
+  uint16_t b[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    b[e] = to_bf16(v.x[e]);
+    r.x[e] = from_bf16(b[e]);
+  }
+  if constexpr (V == 4) {
+    *reinterpret_cast<uint2*>(p) = make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                                              (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<uint32_t*>(p) = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+  } else {
+    *p = b[0];
+  }
+  return r;
+}
+
+// sum over the four waves, in wave order, of the values each lane left in sh
+template <int V>
+__device__ __forceinline__ vec<V> sum4(float (*sh)[kTileF * 4], int lane) {
+  vec<V> r;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const int o = lane * V + e;
+    r.x[e] = (sh[0][o] + sh[1][o]) + (sh[2][o] + sh[3][o]);
+  }
+  return r;
+}
+
+template <int V>
+__device__ __forceinline__ void put(float (*sh)[kTileF * 4], int w, int lane, const vec<V>& v) {
+#pragma unroll
+  for (int e = 0; e < V; ++e) sh[w][lane * V + e] = v.x[e];
+}
+
+template <int V>
+__device__ __forceinline__ vec<V> zero() {
+  vec<V> r;
+#pragma unroll
+  for (int e = 0; e < V; ++e) r.x[e] = 0.f;
+  return r;
 }
 
 // Forward normalisation statistics of colouring c over its k class rows of
 // v = z + u[c] + beta: the mean and the sum of squared deviations (two
 // passes; the second re-reads the block's rows from cache).
+template <int V>
 __global__ __launch_bounds__(256) void inv_fwd_stats_kernel(const float* __restrict__ z, const float* __restrict__ u,
                                                             const float* __restrict__ beta, int32_t k, int32_t l,
                                                             float* __restrict__ pmean, float* __restrict__ pm2) {
-  __shared__ float sh[4][kTileF];
+  __shared__ float sh[4][kTileF * 4];
   const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int f = blockIdx.x * kTileF + lane;
+  const int f = (blockIdx.x * kTileF + lane) * V;
   const bool ok = f < l;
-  const float add = ok ? u[(size_t)c * l + f] + beta[f] : 0.f;
+  vec<V> add = zero<V>(), s = zero<V>(), q = zero<V>();
   const float* zc = z + (size_t)c * k * l + f;
-  float s = 0.f;
-  if (ok)
+  if (ok) {
+    const vec<V> uu = ldv<V>(u + (size_t)c * l + f), bb = ldv<V>(beta + f);
+#pragma unroll
+    for (int e = 0; e < V; ++e) add.x[e] = uu.x[e] + bb.x[e];
 #pragma unroll 4
-    for (int i = w; i < k; i += 4) s += zc[(size_t)i * l];
-  sh[w][lane] = s;
+    for (int i = w; i < k; i += 4) {
+      const vec<V> t = ldv<V>(zc + (size_t)i * l);
+#pragma unroll
+      for (int e = 0; e < V; ++e) s.x[e] += t.x[e];
+    }
+  }
+  put<V>(sh, w, lane, s);
   __syncthreads();
-  const float m = sum4(sh, lane) / (float)k + add;
-  float q = 0.f;
+  vec<V> m = sum4<V>(sh, lane);
+#pragma unroll
+  for (int e = 0; e < V; ++e) m.x[e] = m.x[e] / (float)k + add.x[e];
   if (ok)
 #pragma unroll 4
     for (int i = w; i < k; i += 4) {
-      const float d = zc[(size_t)i * l] + add - m;
-      q += d * d;
+      const vec<V> t = ldv<V>(zc + (size_t)i * l);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float d = t.x[e] + add.x[e] - m.x[e];
+        q.x[e] += d * d;
+      }
     }
   __syncthreads();
-  sh[w][lane] = q;
+  put<V>(sh, w, lane, q);
   __syncthreads();
   if (w == 0 && ok) {
-    pmean[(size_t)c * l + f] = m;
-    pm2[(size_t)c * l + f] = sum4(sh, lane);
+    stv<V>(pmean + (size_t)c * l + f, m);
+    stv<V>(pm2 + (size_t)c * l + f, sum4<V>(sh, lane));
   }
 }
 
@@ -176,6 +265,7 @@ __global__ __launch_bounds__(1024) void inv_colsum_kernel(const float* __restric
 // Normalise, scale, shift and activate the k class rows of colouring c:
 // X'[c k + i][f] = LReLU((z + u[c] + beta - mean) / sqrt(var + eps) gamma + mu)
 // in BF16, and the class mean of the next layer R'[c][f] from those values.
+template <int V>
 __global__ __launch_bounds__(256) void inv_fwd_apply_kernel(const float* __restrict__ z, const float* __restrict__ u,
                                                             const float* __restrict__ beta,
                                                             const float* __restrict__ mean,
@@ -183,27 +273,46 @@ __global__ __launch_bounds__(256) void inv_fwd_apply_kernel(const float* __restr
                                                             const float* __restrict__ gamma,
                                                             const float* __restrict__ mu, int32_t k, int32_t l,
                                                             uint16_t* __restrict__ xn, uint16_t* __restrict__ rn) {
-  __shared__ float sh[4][kTileF];
+  __shared__ float sh[4][kTileF * 4];
   const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int f = blockIdx.x * kTileF + lane;
+  const int f = (blockIdx.x * kTileF + lane) * V;
   const bool ok = f < l;
-  float r = 0.f;
+  vec<V> r = zero<V>();
   if (ok) {
-    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh_ = mu[f];
+    vec<V> a, rs, g, sf;
+    const vec<V> uu = ldv<V>(u + (size_t)c * l + f), bb = ldv<V>(beta + f), mm = ldv<V>(mean + f),
+                 vv = ldv<V>(var + f), gg = ldv<V>(gamma + f), ss = ldv<V>(mu + f);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      a.x[e] = uu.x[e] + bb.x[e];
+      rs.x[e] = 1.f / sqrtf(vv.x[e] + kBnEps);
+      g.x[e] = gg.x[e];
+      sf.x[e] = ss.x[e];
+    }
     const size_t base = (size_t)c * k * l + f;
 #pragma unroll 4
     for (int i = w; i < k; i += 4) {
-      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-      const float y = zh * g + sh_;
-      const uint16_t xb = to_bf16(y > 0.f ? y : kInvSlope * y);
-      xn[base + (size_t)i * l] = xb;
-      r += from_bf16(xb);
+      const vec<V> t = ldv<V>(z + base + (size_t)i * l);
+      vec<V> y;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float zh = (t.x[e] + a.x[e] - mm.x[e]) * rs.x[e];
+        const float yy = zh * g.x[e] + sf.x[e];
+        y.x[e] = yy > 0.f ? yy : kInvSlope * yy;
+      }
+      const vec<V> xb = stv_bf16<V>(xn + base + (size_t)i * l, y);
+#pragma unroll
+      for (int e = 0; e < V; ++e) r.x[e] += xb.x[e];
     }
   }
-  sh[w][lane] = r;
+  put<V>(sh, w, lane, r);
   __syncthreads();
-  if (w == 0 && ok) rn[(size_t)c * l + f] = to_bf16(sum4(sh, lane) / (float)k);
+  if (w == 0 && ok) {
+    vec<V> t = sum4<V>(sh, lane);
+#pragma unroll
+    for (int e = 0; e < V; ++e) t.x[e] /= (float)k;
+    stv_bf16<V>(rn + (size_t)c * l + f, t);
+  }
 }
 
 // Output layer (width 1), one block per colouring c: z_i = X[c k + i] . lambda
@@ -306,6 +415,31 @@ __global__ __launch_bounds__(256) void inv_out_dx_kernel(const float* __restrict
 // dR / k term is the class-mean path of the layer above), the partial sums
 // of dY and dY zhat; summed over colourings these are the gradients of mu
 // and gamma.
+template <int V>
+struct bn_lane {  // per-feature constants of the normalisation backward
+  vec<V> a, m, rs, g, sf, drk;
+};
+
+template <int V>
+__device__ __forceinline__ bn_lane<V> bn_load(const float* u, const float* beta, const float* mean, const float* var,
+                                              const float* gamma, const float* mu, const float* dr, int c, int k,
+                                              int l, int f) {
+  bn_lane<V> b;
+  const vec<V> uu = ldv<V>(u + (size_t)c * l + f), bb = ldv<V>(beta + f), vv = ldv<V>(var + f),
+               dd = ldv<V>(dr + (size_t)c * l + f);
+  b.m = ldv<V>(mean + f);
+  b.g = ldv<V>(gamma + f);
+  b.sf = ldv<V>(mu + f);
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    b.a.x[e] = uu.x[e] + bb.x[e];
+    b.rs.x[e] = 1.f / sqrtf(vv.x[e] + kBnEps);
+    b.drk.x[e] = dd.x[e] / (float)k;
+  }
+  return b;
+}
+
+template <int V>
 __global__ __launch_bounds__(256) void inv_bwd_stats_kernel(const float* __restrict__ dx, const float* __restrict__ dr,
                                                             const float* __restrict__ z, const float* __restrict__ u,
                                                             const float* __restrict__ beta,
@@ -314,37 +448,40 @@ __global__ __launch_bounds__(256) void inv_bwd_stats_kernel(const float* __restr
                                                             const float* __restrict__ gamma,
                                                             const float* __restrict__ mu, int32_t k, int32_t l,
                                                             float* __restrict__ p1, float* __restrict__ p2) {
-  __shared__ float sh1[4][kTileF], sh2[4][kTileF];
+  __shared__ float sh1[4][kTileF * 4], sh2[4][kTileF * 4];
   const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int f = blockIdx.x * kTileF + lane;
+  const int f = (blockIdx.x * kTileF + lane) * V;
   const bool ok = f < l;
-  float s1 = 0.f, s2 = 0.f;
+  vec<V> s1 = zero<V>(), s2 = zero<V>();
   if (ok) {
-    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
-    const float drk = dr[(size_t)c * l + f] / (float)k;
+    const bn_lane<V> b = bn_load<V>(u, beta, mean, var, gamma, mu, dr, c, k, l, f);
     const size_t base = (size_t)c * k * l + f;
 #pragma unroll 4
     for (int i = w; i < k; i += 4) {
-      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-      const float y = zh * g + sh;
-      const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
-      s1 += dy;
-      s2 += dy * zh;
+      const vec<V> t = ldv<V>(z + base + (size_t)i * l), d = ldv<V>(dx + base + (size_t)i * l);
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float zh = (t.x[e] + b.a.x[e] - b.m.x[e]) * b.rs.x[e];
+        const float y = zh * b.g.x[e] + b.sf.x[e];
+        const float dy = (d.x[e] + b.drk.x[e]) * (y > 0.f ? 1.f : kInvSlope);
+        s1.x[e] += dy;
+        s2.x[e] += dy * zh;
+      }
     }
   }
-  sh1[w][lane] = s1;
-  sh2[w][lane] = s2;
+  put<V>(sh1, w, lane, s1);
+  put<V>(sh2, w, lane, s2);
   __syncthreads();
   if (w == 0 && ok) {
-    p1[(size_t)c * l + f] = sum4(sh1, lane);
-    p2[(size_t)c * l + f] = sum4(sh2, lane);
+    stv<V>(p1 + (size_t)c * l + f, sum4<V>(sh1, lane));
+    stv<V>(p2 + (size_t)c * l + f, sum4<V>(sh2, lane));
   }
 }
 
 // Pass 2: dZ = gamma (N dY - sum dY - zhat sum dY zhat) / (N sqrt(var + eps))
 // in BF16 for the products below, and per colouring dU[c][f] = sum_i dZ (BF16
 // for the Gamma products, FP32 partial for the bias gradient).
+template <int V>
 __global__ __launch_bounds__(256) void inv_bwd_apply_kernel(const float* __restrict__ dx, const float* __restrict__ dr,
                                                             const float* __restrict__ z, const float* __restrict__ u,
                                                             const float* __restrict__ beta,
@@ -356,34 +493,40 @@ __global__ __launch_bounds__(256) void inv_bwd_apply_kernel(const float* __restr
                                                             const float* __restrict__ dgamma, int32_t B, int32_t k,
                                                             int32_t l, uint16_t* __restrict__ dzb,
                                                             uint16_t* __restrict__ dub, float* __restrict__ pdu) {
-  __shared__ float shu[4][kTileF];
+  __shared__ float shu[4][kTileF * 4];
   const int c = blockIdx.y, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int f = blockIdx.x * kTileF + lane;
+  const int f = (blockIdx.x * kTileF + lane) * V;
   const bool ok = f < l;
-  float du = 0.f;
+  vec<V> du = zero<V>();
   if (ok) {
-    const float add = u[(size_t)c * l + f] + beta[f], m = mean[f];
-    const float rs = 1.f / sqrtf(var[f] + kBnEps), g = gamma[f], sh = mu[f];
-    const float drk = dr[(size_t)c * l + f] / (float)k;
-    const float N = (float)B * (float)k, s1 = dmu[f], s2 = dgamma[f];
-    const float scale = g * rs / N;
+    const bn_lane<V> b = bn_load<V>(u, beta, mean, var, gamma, mu, dr, c, k, l, f);
+    const vec<V> s1 = ldv<V>(dmu + f), s2 = ldv<V>(dgamma + f);
+    const float N = (float)B * (float)k;
+    vec<V> scale;
+#pragma unroll
+    for (int e = 0; e < V; ++e) scale.x[e] = b.g.x[e] * b.rs.x[e] / N;
     const size_t base = (size_t)c * k * l + f;
 #pragma unroll 4
     for (int i = w; i < k; i += 4) {
-      const float zh = (z[base + (size_t)i * l] + add - m) * rs;
-      const float y = zh * g + sh;
-      const float dy = (dx[base + (size_t)i * l] + drk) * (y > 0.f ? 1.f : kInvSlope);
-      const float v = scale * (N * dy - s1 - zh * s2);
-      dzb[base + (size_t)i * l] = to_bf16(v);
-      du += v;
+      const vec<V> t = ldv<V>(z + base + (size_t)i * l), d = ldv<V>(dx + base + (size_t)i * l);
+      vec<V> v;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const float zh = (t.x[e] + b.a.x[e] - b.m.x[e]) * b.rs.x[e];
+        const float y = zh * b.g.x[e] + b.sf.x[e];
+        const float dy = (d.x[e] + b.drk.x[e]) * (y > 0.f ? 1.f : kInvSlope);
+        v.x[e] = scale.x[e] * (N * dy - s1.x[e] - zh * s2.x[e]);
+        du.x[e] += v.x[e];
+      }
+      stv_bf16<V>(dzb + base + (size_t)i * l, v);
     }
   }
-  shu[w][lane] = du;
+  put<V>(shu, w, lane, du);
   __syncthreads();
   if (w == 0 && ok) {
-    const float t = sum4(shu, lane);
-    dub[(size_t)c * l + f] = to_bf16(t);
-    pdu[(size_t)c * l + f] = t;
+    const vec<V> t = sum4<V>(shu, lane);
+    stv_bf16<V>(dub + (size_t)c * l + f, t);
+    stv<V>(pdu + (size_t)c * l + f, t);
   }
 }
 
@@ -420,6 +563,7 @@ struct dlm_invnet {
   std::vector<int> lin, lout;
   // packed FP32 trainables per layer: L, G, beta, then gamma, mu (hidden layers)
   std::vector<int64_t> oL, oG, ob, og, om, oLb, oGb, orm, orv;
+  std::vector<int> vw;  // vector width of each hidden layer's per-colouring kernels
   int64_t total = 0, nbf = 0, nrun = 0;
   float *P = nullptr, *M = nullptr, *V = nullptr, *Gr = nullptr, *run = nullptr;
   uint16_t* Pb = nullptr;  // BF16 copies of every L and G
@@ -468,6 +612,20 @@ int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inn
 unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
 unsigned col_blocks(int64_t l) { return (unsigned)((l + kTileF - 1) / kTileF); }
 
+// launch a per-colouring kernel with the layer's vector width (4, 2 or 1)
+#define INV_VLAUNCH(kern, V, l, B, st, ...)                                                                  \
+  do {                                                                                                      \
+    if ((V) == 4)                                                                                           \
+      hipLaunchKernelGGL(kern<4>, dim3((unsigned)(((l) + 4 * kTileF - 1) / (4 * kTileF)), (unsigned)(B)), \
+                         dim3(256), 0, st, __VA_ARGS__);                                                    \
+    else if ((V) == 2)                                                                                      \
+      hipLaunchKernelGGL(kern<2>, dim3((unsigned)(((l) + 2 * kTileF - 1) / (2 * kTileF)), (unsigned)(B)), \
+                         dim3(256), 0, st, __VA_ARGS__);                                                    \
+    else                                                                                                    \
+      hipLaunchKernelGGL(kern<1>, dim3((unsigned)(((l) + kTileF - 1) / kTileF), (unsigned)(B)), dim3(256), \
+                         0, st, __VA_ARGS__);                                                               \
+  } while (0)
+
 // forward of a batch of B colourings; train: BN from the batch statistics
 // (and, with update, the running estimates moved), else from the running
 // estimates
@@ -488,19 +646,17 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
     int rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
     if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
     if (rc != DLM_OK) return rc;
-    const dim3 tiles((unsigned)((lo + kTileF - 1) / kTileF), (unsigned)B);
     const float* mean = s->run + s->orm[j];
     const float* var = s->run + s->orv[j];
     if (train) {
-      hipLaunchKernelGGL(inv_fwd_stats_kernel, tiles, dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], k, lo,
-                         s->pa, s->pb);
+      INV_VLAUNCH(inv_fwd_stats_kernel, s->vw[j], lo, B, st, s->Z[j], s->U[j], s->P + s->ob[j], k, lo, s->pa, s->pb);
       hipLaunchKernelGGL(inv_fwd_stats_final_kernel, dim3(col_blocks(lo)), dim3(1024), 0, st, s->pa, s->pb, B, k, lo,
                          s->mean[j], s->var[j], s->run + s->orm[j], s->run + s->orv[j], update ? 1 : 0);
       mean = s->mean[j];
       var = s->var[j];
     }
-    hipLaunchKernelGGL(inv_fwd_apply_kernel, tiles, dim3(256), 0, st, s->Z[j], s->U[j], s->P + s->ob[j], mean, var,
-                       s->P + s->og[j], s->P + s->om[j], k, lo, s->X[j + 1], s->R[j + 1]);
+    INV_VLAUNCH(inv_fwd_apply_kernel, s->vw[j], lo, B, st, s->Z[j], s->U[j], s->P + s->ob[j], mean, var,
+                s->P + s->og[j], s->P + s->om[j], k, lo, s->X[j + 1], s->R[j + 1]);
   }
   DLM_HIP(hipGetLastError());
   return DLM_OK;
@@ -515,7 +671,6 @@ int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStr
   for (int j = jo; j >= 0; --j) {
     const int li = s->lin[j], lo = s->lout[j];
     const dim3 tiles((unsigned)((li + 255) / 256), (unsigned)B);
-    const dim3 ftiles((unsigned)((li + kTileF - 1) / kTileF), (unsigned)B);
     if (j == jo) {  // width 1: no GEMM
       hipLaunchKernelGGL(inv_out_grad_kernel, tiles, dim3(256), 0, st, s->X[j], s->R[j], s->df, k, li, s->pa, s->pb);
       hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, s->pb, B, li,
@@ -536,12 +691,12 @@ int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStr
     const int p = j - 1;
     float* dmu = s->Gr + s->om[p];
     float* dgamma = s->Gr + s->og[p];
-    hipLaunchKernelGGL(inv_bwd_stats_kernel, ftiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
-                       s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], k, li, s->pa, s->pb);
+    INV_VLAUNCH(inv_bwd_stats_kernel, s->vw[p], li, B, st, s->dX, s->dR, s->Z[p], s->U[p], s->P + s->ob[p],
+                s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], k, li, s->pa, s->pb);
     hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, s->pb, B, li, dmu, dgamma);
-    hipLaunchKernelGGL(inv_bwd_apply_kernel, ftiles, dim3(256), 0, st, s->dX, s->dR, s->Z[p], s->U[p],
-                       s->P + s->ob[p], s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], dmu, dgamma, B, k,
-                       li, s->dZb, s->dUb, s->pa);
+    INV_VLAUNCH(inv_bwd_apply_kernel, s->vw[p], li, B, st, s->dX, s->dR, s->Z[p], s->U[p], s->P + s->ob[p],
+                s->mean[p], s->var[p], s->P + s->og[p], s->P + s->om[p], dmu, dgamma, B, k, li, s->dZb, s->dUb,
+                s->pa);
     hipLaunchKernelGGL(inv_colsum_kernel, dim3(col_blocks(li)), dim3(1024), 0, st, s->pa, (const float*)nullptr, B, li,
                        s->Gr + s->ob[p], (float*)nullptr);
   }
@@ -572,12 +727,12 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
                       int32_t max_batch, dlm_invnet** out) {
   if (!out || !widths || !params_host) return set_error(DLM_E_INVAL, "dlm_invnet_create: null argument");
   *out = nullptr;
-  if (n < 1 || n > 32767 || k < 2 || k > 32767 || nl < 1 || nl > 64 || max_batch < 1 || max_batch > 65536)
+  if (n < 1 || n > 32767 || k < 2 || k > 32767 || nl < 1 || nl > 64 || max_batch < 1 || max_batch > 65535)
     return set_error(DLM_E_INVAL, "dlm_invnet_create: n=%d k=%d layers=%d max_batch=%d", n, k, nl, max_batch);
   if (widths[nl - 1] != 1) return set_error(DLM_E_INVAL, "dlm_invnet_create: the last layer must have width 1");
   for (int j = 0; j < nl; ++j)
     if (widths[j] < 1 || widths[j] > 65536) return set_error(DLM_E_INVAL, "dlm_invnet_create: width %d", widths[j]);
-  if ((int64_t)max_batch * k > 0x7fffffffll / 65536)
+  if ((int64_t)max_batch * k > 0x7fffffffll)  // class rows of one pass: a 32-bit GEMM dimension and grid size
     return set_error(DLM_E_INVAL, "dlm_invnet_create: max_batch * k too large");
   dlm_invnet* s = new dlm_invnet();
   s->n = n;
@@ -620,6 +775,23 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
   s->total = o;
   s->nbf = ob16;
   s->nrun = orun;
+  // vector width per hidden layer: the widest of 4, 2, 1 that divides the
+  // width and every packed offset the per-colouring kernels read or write
+  // (activation buffers are 256-byte aligned and their rows l values long)
+  for (int j = 0; j < nl; ++j) {
+    int v = 1;
+    if (j < nl - 1)
+      for (int c : {4, 2}) {
+        const int64_t offs[] = {s->lout[j], s->ob[j], s->og[j], s->om[j], s->orm[j], s->orv[j]};
+        bool fit = true;
+        for (int64_t x : offs) fit = fit && x % c == 0;
+        if (fit) {
+          v = c;
+          break;
+        }
+      }
+    s->vw.push_back(v);
+  }
   const int64_t B = max_batch, N = B * k;
   // one allocation: P, M, V, Gr, run (FP32), Pb (BF16), activations, backward buffers
   std::vector<std::pair<void**, int64_t>> parts;

@@ -58,7 +58,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         epochs: int = 5, lr: float = 1e-3, block: int = 0, table: str = "auto",
         log=None, diversity: bool = False, neighbours: int = 16,
         init_colors: torch.Tensor | None = None, weighted: bool = False, rounds: int = 10,
-        target: int | None = None) -> MemeticResult:
+        target: int | None = None, network: str = "mlp", eval_chunk: int = 256) -> MemeticResult:
     """One loop of Algorithm 1.  With ``weighted`` it solves the WVCP
     (Section 2.2): the start is the greedy colouring (k = 0 takes the largest
     number of colours it uses), the local search is Algorithm 2 with
@@ -66,7 +66,14 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
     individual's score is its best legal weighted score.  The loop stops when
     the best score reaches ``target`` (default 0 for k-COL, none for WVCP),
     at ``max_generations`` or at the cutoff; ``time_to_legal`` is then the
-    time the target was reached."""
+    time the target was reached.
+
+    ``network`` picks the learned loop's scorer: "mlp" is the per-class MLP
+    with sum pooling (dlm_scorer, ``scorer_params`` its packed weights);
+    "invariant" is the paper's colour-invariant network of Section 2.3
+    (dlm_invnet, ``scorer_params`` its weights with a "widths" entry),
+    trained at ``batch`` colourings per step and evaluated in chunks of
+    ``eval_chunk``."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if target is None:
         target = -1 if weighted else 0
@@ -80,6 +87,8 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         raise ValueError("this loop keeps the population size: children_per_pair * keep_frac must be 1")
     if learned and scorer_params is None:
         raise ValueError("the learned loop needs initial scorer parameters")
+    if network not in ("mlp", "invariant"):
+        raise ValueError(f"unknown network {network!r}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     if init_colors is not None:
@@ -107,7 +116,11 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
     res.history.append((now, 0, best, float(f.float().mean().item())))
     if best <= target:
         res.time_to_legal = now
-    sc = A.Scorer(graph.n, k, scorer_params, max_batch=batch) if learned else None
+    sc = None
+    if learned and network == "mlp":
+        sc = A.Scorer(graph.n, k, scorer_params, max_batch=batch)
+    elif learned:
+        sc = A.InvNet(graph.n, k, scorer_params["widths"], scorer_params, max_batch=max(batch, eval_chunk))
     off = torch.empty((nsel, graph.n), dtype=torch.int16, device=dev)
     start = torch.empty_like(off)
     if diversity:
@@ -167,6 +180,8 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
     res.colors, res.f = cols, f
     if sc is not None:
         res.scorer_params = sc.params()
+        if network == "invariant":
+            res.scorer_params["widths"] = list(scorer_params["widths"])
     res.wall = time.perf_counter() - t0
     return res
 

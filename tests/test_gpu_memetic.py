@@ -137,6 +137,29 @@ def test_short_memetic_loop_diversity(dlm, dev, learned):
         assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()
 
 
+def test_memetic_loop_invariant_network(dlm, dev):
+    """The learned loop with the paper's colour-invariant network as scorer
+    (k-COL widths for 120 vertices), with the diversity steps: the loop runs,
+    its scores are the conflicts of its population, the network's losses are
+    finite, and its parameters (with the widths) come back for the next k."""
+    from paper_2109_05948_amd import memetic
+    from workloads.invnet_init import col_widths, invnet_weights
+    g = gnp(120, 0.5, seed=3)
+    k, pop = 16, 64
+    G = dlm.Graph.from_csr(g)
+    params = invnet_weights(g.n, col_widths(g.n), seed=0)
+    params["widths"] = col_widths(g.n)
+    say("memetic invariant network")
+    res = memetic.run(G, k, pop, 600, learned=True, seed=1, cutoff_s=60, max_generations=3, scorer_params=params,
+                      batch=32, epochs=2, diversity=True, neighbours=8, network="invariant", eval_chunk=96)
+    conf, _ = dlm.evaluate(G, res.colors, k)
+    assert (conf == res.f).all() and res.best == int(res.f.min().item())
+    if res.generations:
+        assert len(res.scorer_loss) == res.generations and np.isfinite(res.scorer_loss).all()
+    assert res.scorer_params["widths"] == col_widths(g.n)
+    assert res.scorer_params["L1"].shape == (10 * g.n, 5 * g.n)
+
+
 def test_reduce_colours(dlm, dev):
     from oracle import reduce as rd
     rng = np.random.default_rng(8)
