@@ -154,6 +154,9 @@ def main():
                          "colour-invariant network at its k-COL depth)")
     ap.add_argument("--epochs", type=int, default=0,
                     help="memetic1000: training epochs per generation (default: the workload's)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="invnet: choose the GEMM solutions by measurement before timing (1) or keep the "
+                         "library's defaults (0)")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
@@ -382,7 +385,8 @@ def bench_memetic(args, w, dlm, torch):
                             cutoff_s=args.cutoff, children_per_pair=e["children_per_pair"],
                             keep_frac=e["keep_frac"], scorer_params=params, batch=batch, epochs=epochs,
                             lr=e["lr"], log=log, diversity=args.diversity > 0,
-                            neighbours=max(args.diversity, 1), network=args.network)
+                            neighbours=max(args.diversity, 1), network=args.network,
+                            tune_gemms=bool(args.tune))
             runs.append({"seed": sd, "time_to_legal_s": r.time_to_legal, "best_f": r.best,
                          "generations": r.generations, "wall_s": r.wall,
                          "tabu_moves_per_s": r.tabu_moves / r.wall,
@@ -656,6 +660,11 @@ def bench_invnet(args, w, dlm, torch):
     tgt = torch.randn(p, generator=gen).to("cuda")
     scores = torch.empty(p, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
+    if args.tune:
+        t_ = time.perf_counter()
+        for b_ in sorted({batch, chunk, p % batch, p % chunk} - {0}):
+            net.tune(b_)
+        log(f"GEMM solutions tuned in {time.perf_counter() - t_:.1f} s")
     for s_ in range(args.warmup):
         log(f"warmup step {s_}")
         net.forward(col, out=scores)
@@ -684,7 +693,8 @@ def bench_invnet(args, w, dlm, torch):
            "warmup": args.warmup, "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
            "config": {"workload": "invnet", "graph": "G(n=500, p=0.5) seed 0", "k": k, "widths": widths,
-                      "colourings": p, "batch": batch, "eval_chunk": chunk, "epochs": 1},
+                      "colourings": p, "batch": batch, "eval_chunk": chunk, "epochs": 1,
+                      "gemm_solutions": "tuned" if args.tune else "default"},
            "inference_ms": inf_ms, "train_epoch_ms": tr_ms,
            "train_pairs_per_s": p / (tr_ms * 1e-3),
            "roofline": {"bound": "mfma", "achieved": inf_tf, "peak": 2500.0, "unit": "TFLOP/s",

@@ -544,6 +544,19 @@ int dlm_invnet_grad(dlm_invnet* s, const int16_t* colors_dev, const float* targe
 int dlm_invnet_train(dlm_invnet* s, const int16_t* colors_dev, const float* targets_dev, int32_t count,
                      int32_t batch, int32_t epochs, float lr, float* loss_dev, void* stream);
 
+/*
+ * Choose the GEMM kernels of the network by measurement: for every product
+ * of a training pass at `batch` colourings (forward and backward; the
+ * evaluation of a chunk of that size uses the forward ones), time each
+ * solution the GEMM library lists for the call, and its default choice, on
+ * `stream`, and use the fastest from then on.  Shapes not tuned keep the
+ * default.  Synchronises the stream; the trial launches write only the
+ * network's scratch buffers.  The choice depends on timing and so may differ
+ * between runs and machines; every solution accumulates in FP32, but the
+ * summation order (and so the last bits) can differ from the default's.
+ */
+int dlm_invnet_tune(dlm_invnet* s, int32_t batch, void* stream);
+
 /* ------------------------------------------------------------------------
  * Measurement helper (not part of the search): sustained LDS read bandwidth
  * of the whole device in bytes/s, from a kernel that streams conflict-free

@@ -36,7 +36,7 @@ EXPORTS = [
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
     "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours", "dlm_invnet_create",
     "dlm_invnet_destroy", "dlm_invnet_num_params", "dlm_invnet_get_params", "dlm_invnet_forward",
-    "dlm_invnet_grad", "dlm_invnet_train",
+    "dlm_invnet_grad", "dlm_invnet_train", "dlm_invnet_tune",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
             L.dlm_invnet_forward.argtypes = [P, P, I32, P, P]
             L.dlm_invnet_grad.argtypes = [P, P, P, I32, P, P, P]
             L.dlm_invnet_train.argtypes = [P, P, P, I32, I32, I32, C.c_float, P, P]
+            L.dlm_invnet_tune.argtypes = [P, I32, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -431,6 +432,10 @@ class InvNet:
         return out
 
     score = forward  # the scorer interface of the memetic loop
+
+    def tune(self, batch: int, stream=None):
+        """dlm_invnet_tune: pick the fastest GEMM solutions for passes of `batch` colourings."""
+        _check("dlm_invnet_tune", lib().dlm_invnet_tune(self._h, batch, _stream(stream)))
 
     def grad(self, colors: torch.Tensor, targets: torch.Tensor, stream=None):
         """dlm_invnet_grad -> (flat FP32 gradient of the batch MSE, loss)."""

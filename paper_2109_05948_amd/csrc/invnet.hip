@@ -12,8 +12,12 @@
 // output) and goes to rocBLAS; the one-hot input, class means, broadcasts,
 // normalisation, activation, loss, their backward steps and Adam are the
 // kernels below.  All reductions run in a fixed order.
+#define ROCBLAS_BETA_FEATURES_API  // solution listing for measured GEMM choice
+#define ROCBLAS_NO_DEPRECATED_WARNINGS
 #include <rocblas/rocblas.h>
 
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "dlm_common.h"
@@ -579,17 +583,84 @@ struct dlm_invnet {
   int adam_t = 0;
   void* ws = nullptr;
   rocblas_handle h = nullptr;
+  // GEMM solution per (transA, transB, m, n, k), chosen by dlm_invnet_tune;
+  // shapes not in the map use the library's default choice
+  std::map<std::tuple<int, int, int, int, int>, int32_t> solution;
+  bool tuning = false;
+  hipStream_t tune_stream = nullptr;
 };
 
 namespace {
 
+rocblas_status gemm_call(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+                         const void* A, int lda, const void* B, int ldb, float beta, float* C, int ldc,
+                         int32_t sol) {
+  const float alpha = 1.f;
+  return rocblas_gemm_ex(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r,
+                         ldb, &beta, C, rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc,
+                         rocblas_datatype_f32_r, sol >= 0 ? rocblas_gemm_algo_solution_index : rocblas_gemm_algo_standard,
+                         sol >= 0 ? sol : 0, 0);
+}
+
+// time every solution rocBLAS lists for this call (and its default) on the
+// tuning stream and keep the fastest; the call's buffers are the network's
+// own scratch, so the trial launches change nothing that persists
+int tune_gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A, int lda,
+              const void* B, int ldb, float beta, float* C, int ldc) {
+  const auto key = std::make_tuple((int)ta, (int)tb, m, n, k);
+  if (s->solution.count(key)) return DLM_OK;
+  const float alpha = 1.f;
+  rocblas_int cnt = 0;
+  if (rocblas_gemm_ex_get_solutions(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B,
+                                    rocblas_datatype_bf16_r, ldb, &beta, C, rocblas_datatype_f32_r, ldc, C,
+                                    rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
+                                    rocblas_gemm_algo_solution_index, 0, nullptr, &cnt) != rocblas_status_success)
+    cnt = 0;
+  std::vector<rocblas_int> list((size_t)cnt);
+  if (cnt > 0 &&
+      rocblas_gemm_ex_get_solutions(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B,
+                                    rocblas_datatype_bf16_r, ldb, &beta, C, rocblas_datatype_f32_r, ldc, C,
+                                    rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
+                                    rocblas_gemm_algo_solution_index, 0, list.data(), &cnt) != rocblas_status_success)
+    cnt = 0;
+  list.resize((size_t)cnt);
+  list.insert(list.begin(), -1);  // the default choice
+  hipEvent_t e0, e1;
+  DLM_HIP(hipEventCreate(&e0));
+  DLM_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int32_t pick = -1;
+  for (int32_t sol : list) {
+    if (gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) != rocblas_status_success) continue;
+    constexpr int kReps = 3;
+    (void)hipEventRecord(e0, s->tune_stream);
+    bool ok = true;
+    for (int r = 0; r < kReps && ok; ++r)
+      ok = gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) == rocblas_status_success;
+    (void)hipEventRecord(e1, s->tune_stream);
+    if (hipEventSynchronize(e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return set_error(DLM_E_HIP, "dlm_invnet_tune: event synchronisation failed");
+    }
+    float ms = 0.f;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
+      best = ms;
+      pick = sol;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->solution[key] = pick;
+  return DLM_OK;
+}
+
 int gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A, int lda,
          const void* B, int ldb, float beta, float* C, int ldc) {
-  const float alpha = 1.f;
-  const rocblas_status st =
-      rocblas_gemm_ex(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r, ldb,
-                      &beta, C, rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
-                      rocblas_gemm_algo_standard, 0, 0);
+  if (s->tuning) return tune_gemm(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc);
+  const auto it = s->solution.find(std::make_tuple((int)ta, (int)tb, m, n, k));
+  const int32_t sol = it == s->solution.end() ? -1 : it->second;
+  const rocblas_status st = gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol);
   if (st != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_gemm_ex failed (%d)", (int)st);
   return DLM_OK;
 }
@@ -929,6 +1000,30 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets,
       DLM_HIP(hipGetLastError());
       ++step;
     }
+  return rc;
+}
+
+int dlm_invnet_tune(dlm_invnet* s, int32_t batch, void* stream) {
+  if (!s || batch < 1 || batch > s->max_batch)
+    return set_error(DLM_E_INVAL, "dlm_invnet_tune: batch=%d (need 1..max_batch)", batch);
+  hipStream_t st = (hipStream_t)stream;
+  int rc = set_stream(s, st);
+  if (rc != DLM_OK) return rc;
+  const int B = batch, N = batch * s->k;
+  s->tuning = true;
+  s->tune_stream = st;
+  // every product of a training pass (forward and backward) at this batch;
+  // evaluation uses the forward ones
+  for (int j = 0; rc == DLM_OK && j + 1 < s->nl; ++j) {
+    const int li = s->lin[j], lo = s->lout[j];
+    rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], N, li, lo, s->Z[j]);
+    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
+    if (rc == DLM_OK) rc = mm_at(s, s->X[j], s->dZb, N, li, lo, s->Gr + s->oL[j]);
+    if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
+    if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], N, li, lo, s->dX);
+    if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
+  }
+  s->tuning = false;
   return rc;
 }
 

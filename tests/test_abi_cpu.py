@@ -120,4 +120,5 @@ def test_invnet_argument_checks(L):
     assert L.dlm_invnet_grad(None, None, None, 1, None, None, None) == -1
     assert L.dlm_invnet_train(None, None, None, 1, 1, 1, C.c_float(1e-3), None, None) == -1
     assert L.dlm_invnet_get_params(None, None, None) == -1
+    assert L.dlm_invnet_tune(None, 1, None) == -1
     assert L.dlm_invnet_destroy(None) == 0

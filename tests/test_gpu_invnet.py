@@ -309,3 +309,32 @@ def test_paper_depth_sampled(dlm, dev):
     assert np.isfinite(losses).all()
     after = net.params()
     assert all(np.isfinite(after[nm]).all() for nm in net.run_names)
+
+
+def test_tuned_products(dlm, dev):
+    """After the GEMM solutions are chosen by measurement (training batch and
+    evaluation chunk), evaluation and gradients still follow the oracle."""
+    n, k, widths, b = 130, 7, [200, 70, 70, 1], 24
+    rng = np.random.default_rng(21)
+    colors = rng.integers(0, k, size=(b, n)).astype(np.int16)
+    targets = rng.normal(0, 1, size=b).astype(np.float32)
+    P = f32(calibrated(params(n, widths, 22), colors, k, 23))
+    say("invnet tuned products")
+    net = dlm.InvNet(n, k, widths, P, max_batch=b)
+    net.tune(b)
+    net.tune(b // 3)
+    got = net.forward(cuda(colors)).cpu().numpy()
+    want, _ = ref.forward(P, colors, k, train=False)
+    dv = deviation(lambda q: {"f": ref.forward(P, colors, k, train=False, q=q)[0]}, {"f": want})
+    close(got, want, dv["f"], "tuned forward")
+    g, _ = net.grad(cuda(colors), cuda(targets))
+    g = net.unpack(g.cpu().numpy(), net.train_names)
+
+    def run(q):
+        f, cache = ref.forward(P, colors, k, train=True, q=q)
+        return ref.backward(P, cache, 2.0 * (f - targets) / b, k, q=q)
+
+    wg = run(None)
+    dg = deviation(run, wg)
+    for nm in ("L0", "G0", "L1", "G1", "L2", "G2", "L3", "G3", "g0", "m0", "g1", "m1"):
+        close(g[nm], wg[nm], dg[nm], nm)
