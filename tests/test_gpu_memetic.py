@@ -215,3 +215,27 @@ def test_weighted_memetic_loop(dlm, dev, learned):
     legal = (res.f != 0x7fffffff)
     assert legal.any() and (conf[legal] == 0).all()
     assert (ws[legal] == res.f[legal]).all()
+
+
+def test_weighted_memetic_loop_invariant_network(dlm, dev):
+    """The WVCP loop learning with the paper's network at its WVCP depth
+    (hidden widths 5n, 2n, n, n // 2): scores stay the weighted scores of
+    legal colourings and the network's losses are finite."""
+    from paper_2109_05948_amd import memetic
+    from workloads.graphs import uniform_weights
+    from workloads.invnet_init import invnet_weights, wvcp_widths
+    g = gnp(90, 0.3, seed=4)
+    g = g.with_weights(uniform_weights(90, 1, 100, seed=5))
+    G = dlm.Graph.from_csr(g)
+    params = invnet_weights(g.n, wvcp_widths(g.n), seed=1)
+    params["widths"] = wvcp_widths(g.n)
+    say("weighted memetic invariant network")
+    res = memetic.run(G, 0, 32, 10 * g.n, learned=True, seed=2, cutoff_s=60, max_generations=3,
+                      scorer_params=params, batch=16, epochs=2, weighted=True, rounds=3, network="invariant",
+                      eval_chunk=64)
+    assert res.generations == 3 and len(res.scorer_loss) == 3 and np.isfinite(res.scorer_loss).all()
+    k = int(res.colors.max().item()) + 1
+    conf, ws = dlm.evaluate(G, res.colors, k, weighted=True)
+    legal = (res.f != 0x7fffffff)
+    assert legal.any() and (conf[legal] == 0).all()
+    assert (ws[legal] == res.f[legal]).all()
