@@ -490,9 +490,10 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * normalisation over the batch and all k classes per feature (eps 1e-5,
  * learnable scale gamma_j and shift mu_j per feature, running estimates with
  * momentum 0.1 and the unbiased variance); the last layer has width 1 and
- * the output is (1/k) sum_i Z_i.  Every product is a GEMM with BF16 operands
- * and FP32 accumulation (rocBLAS); everything else runs in FP32 on kernels of
- * this library, reductions in a fixed order.
+ * the output is (1/k) sum_i Z_i.  The hidden layers' products are GEMMs with
+ * BF16 operands and FP32 accumulation (rocBLAS); the output layer's products
+ * and everything else run in FP32 on kernels of this library, reductions in
+ * a fixed order.
  *
  * widths: nl layer widths (hidden ..., 1).  params_host: FP32, per layer
  * Lambda [l_in][l_out], Gamma [l_in][l_out], beta [l_out], then for hidden

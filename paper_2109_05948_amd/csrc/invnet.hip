@@ -8,10 +8,11 @@
 //            statistics in training, running estimates with momentum 0.1 in
 //            evaluation; learnable scale and shift per feature)
 //   output (width 1):  f = class mean of Z.
-// Every product is a plain GEMM (BF16 operands, FP32 accumulation and
-// output) and goes to rocBLAS; the one-hot input, class means, broadcasts,
-// normalisation, activation, loss, their backward steps and Adam are the
-// kernels below.  All reductions run in a fixed order.
+// The products of the hidden layers are plain GEMMs (BF16 operands, FP32
+// accumulation and output) and go to rocBLAS; the width-1 output layer's
+// products (matrix-vector, FP32 weights), the one-hot input, class means,
+// broadcasts, normalisation, activation, loss, their backward steps and
+// Adam are the kernels below.  All reductions run in a fixed order.
 #define ROCBLAS_BETA_FEATURES_API  // solution listing for measured GEMM choice
 #define ROCBLAS_NO_DEPRECATED_WARNINGS
 #include <rocblas/rocblas.h>
@@ -568,7 +569,7 @@ struct dlm_invnet {
   // packed FP32 trainables per layer: L, G, beta, then gamma, mu (hidden layers)
   std::vector<int64_t> oL, oG, ob, og, om, oLb, oGb, orm, orv;
   std::vector<int> vw;  // vector width of each hidden layer's per-colouring kernels
-  int64_t total = 0, nbf = 0, nrun = 0;
+  int64_t total = 0, nrun = 0;
   float *P = nullptr, *M = nullptr, *V = nullptr, *Gr = nullptr, *run = nullptr;
   uint16_t* Pb = nullptr;  // BF16 copies of every L and G
   // activations for max_batch colourings
@@ -805,12 +806,14 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
     if (widths[j] < 1 || widths[j] > 65536) return set_error(DLM_E_INVAL, "dlm_invnet_create: width %d", widths[j]);
   if ((int64_t)max_batch * k > 0x7fffffffll)  // class rows of one pass: a 32-bit GEMM dimension and grid size
     return set_error(DLM_E_INVAL, "dlm_invnet_create: max_batch * k too large");
+  int device = 0;
+  DLM_HIP(hipGetDevice(&device));
   dlm_invnet* s = new dlm_invnet();
   s->n = n;
   s->k = k;
   s->nl = nl;
   s->max_batch = max_batch;
-  DLM_HIP(hipGetDevice(&s->device));
+  s->device = device;
   int64_t o = 0, ob16 = 0, orun = 0, lmax = n;
   for (int j = 0; j < nl; ++j) {
     const int li = j ? widths[j - 1] : n, lo = widths[j];
@@ -844,7 +847,6 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
     }
   }
   s->total = o;
-  s->nbf = ob16;
   s->nrun = orun;
   // vector width per hidden layer: the widest of 4, 2, 1 that divides the
   // width and every packed offset the per-colouring kernels read or write
