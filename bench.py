@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
                     choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity",
-                             "decreasing", "popsweep", "invnet"])
+                             "decreasing", "popsweep", "invnet", "predict"])
     ap.add_argument("--pops", default="256,1024,4096,16384", help="popsweep: population sizes")
     ap.add_argument("--passes", type=int, default=3,
                     help="popsweep: budget = this many local-search passes of the largest population")
@@ -154,6 +154,7 @@ def main():
                          "colour-invariant network at its k-COL depth)")
     ap.add_argument("--epochs", type=int, default=0,
                     help="memetic1000: training epochs per generation (default: the workload's)")
+    ap.add_argument("--generations", type=int, default=16, help="predict: generations per loop")
     ap.add_argument("--tune", type=int, default=1,
                     help="invnet: choose the GEMM solutions by measurement before timing (1) or keep the "
                          "library's defaults (0)")
@@ -195,6 +196,8 @@ def main():
         return bench_diversity(args, workload("gnp500"), dlm, torch)
     if args.workload == "invnet":
         return bench_invnet(args, workload("gnp500"), dlm, torch)
+    if args.workload == "predict":
+        return bench_predict(args, workload("wvcp300"), dlm, torch)
     if args.workload == "popsweep":
         return bench_popsweep(args, workload("wvcp300"), workload("memetic1000"), dlm, torch)
     if args.workload == "decreasing":
@@ -702,6 +705,49 @@ def bench_invnet(args, w, dlm, torch):
                         "flops_per_colouring": inf_f / p, "train_achieved": tr_tf,
                         "train_frac": tr_tf / 2500.0, "train_flops_per_pair": tr_f / p}}
     print(json.dumps(out), flush=True)
+
+def bench_predict(args, w, dlm, torch):
+    """Quality of the learned scorer's predictions inside the WVCP loop (the
+    paper's analysis of its network, Section 4.2): the loop with the
+    diversity steps (K = 32 nearest neighbours, as the paper's WVCP setting)
+    on the weighted G(300, 0.3) stand-in, population 4096, 5 training epochs
+    per generation, once with the per-class MLP and once with the paper's
+    colour-invariant network at its WVCP depth (hidden 5n, 2n, n, n // 2,
+    batch 100).  Each generation records the Pearson correlation between the
+    kept offsprings' predicted and actual scores after the local search, and
+    the median relative error of the predictions."""
+    from paper_2109_05948_amd import memetic
+    from workloads.invnet_init import invnet_weights, wvcp_widths
+    from workloads.scorer_init import scorer_weights
+    g = w.graphs[0]
+    G = dlm.Graph.from_csr(g)
+    pop = args.pop or w.pop
+    out = {}
+    for net in ("mlp", "invariant"):
+        if net == "invariant":
+            params = invnet_weights(g.n, wvcp_widths(g.n), seed=0)
+            params["widths"] = wvcp_widths(g.n)
+            batch = 100
+        else:
+            params, batch = scorer_weights(g.n, seed=0), 1024
+        log(f"predict: WVCP loop with the {net} scorer")
+        r = memetic.run(G, 0, pop, w.iters[0], learned=True, seed=1, cutoff_s=args.cutoff,
+                        max_generations=args.generations, scorer_params=params, batch=batch, epochs=5, lr=1e-3,
+                        log=log, diversity=True, neighbours=32, weighted=True, rounds=w.extra["rounds"],
+                        network=net, tune_gemms=bool(args.tune))
+        out[net] = {"generations": r.generations, "best_wscore": r.best, "wall_s": r.wall,
+                    "per_generation": [{"gen": gg, "pearson": pr, "median_rel_err_pct": re}
+                                       for gg, pr, re in r.predictions]}
+        for gg, pr, re in r.predictions:
+            log(f"  {net} gen {gg}: pearson {pr:.3f}, median relative error {re:.2f} %")
+    line = {"metric": "Pearson correlation of predicted and actual post-search scores (last generation)",
+            "value": out["invariant"]["per_generation"][-1]["pearson"] if out["invariant"]["per_generation"] else None,
+            "unit": "r", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "bf16+fp32",
+            "data": "synthetic",
+            "config": {"workload": "predict", "graph": "G(n=300, p=0.3) seed 0, weights U{1..100}",
+                       "population": pop, "neighbours": 32, "epochs": 5, "generations": args.generations},
+            "networks": out}
+    print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":
     main()

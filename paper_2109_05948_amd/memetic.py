@@ -50,6 +50,33 @@ class MemeticResult:
     colors: object = None  # final population (device int16 [pop, n]) and its scores
     f: object = None
     scorer_params: dict | None = None  # the learned loop's scorer at the end
+    # learned loop, per generation: (generation, Pearson r, median relative
+    # error in %) of the kept offsprings' predicted against actual scores
+    predictions: list = field(default_factory=list)
+
+
+def prediction_quality(pred: torch.Tensor, actual: torch.Tensor, mean: float, sd: float) -> tuple:
+    """The quality measures of the paper's analysis of its network: the
+    Pearson correlation between the predictions and the scores the local
+    search then reached, and the median relative error of the predictions
+    in score units (the network predicts standardised scores; ``mean`` and
+    ``sd`` are those of its last training targets).  Individuals without a
+    finite score (WVCP: no legal colouring) are left out."""
+    a = actual.double()
+    p = pred.double()
+    ok = a < 0x7FFFFFFF
+    a, p = a[ok], p[ok]
+    if a.numel() < 2 or float(a.std()) == 0.0 or float(p.std()) == 0.0:
+        return float("nan"), float("nan")
+    r = float(torch.corrcoef(torch.stack((p, a)))[0, 1])
+    rel = float(((mean + sd * p - a).abs() / a.clamp(min=1.0)).median()) * 100.0
+    return r, rel
+
+
+def _score_scale(f: torch.Tensor) -> tuple:
+    """Mean and population standard deviation, as dlm_standardize takes them."""
+    d = f.double()
+    return float(d.mean()), float(d.std(unbiased=False))
 
 
 def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int = 0,
@@ -135,6 +162,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         first = torch.arange(pop, dtype=torch.int32, device=dev).repeat_interleave(neighbours)
     ind_next = pop
     gen = 0
+    scale = _score_scale(f)  # what the untrained network's outputs are read against
     while best > target and gen < max_generations and time.perf_counter() - t0 < cutoff_s:
         gen += 1
         if diversity:
@@ -145,7 +173,8 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         children = A.gpx_batch(graph, k, cols, pairs, 1 if diversity else children_per_pair, seed ^ SEED_GPX,
                                child_base=gen * nchild)
         if diversity and learned:
-            idx = A.select_groups(sc.score(children), pop, neighbours, "top")
+            scores = sc.score(children)
+            idx = A.select_groups(scores, pop, neighbours, "top")
         elif diversity:
             idx = A.select_groups(None, pop, neighbours, "random", seed=seed ^ SEED_SEL, gen=gen)
         elif learned:
@@ -158,6 +187,8 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         f_off, gen_moves = search(off, ind_next)
         ind_next += nsel
         if learned:
+            res.predictions.append((gen,) + prediction_quality(scores[idx.long()], f_off, *scale))
+            scale = _score_scale(f_off)
             tgt = A.standardize(f_off)
             loss = sc.train(start, tgt, batch=batch, epochs=epochs, lr=lr)
             res.scorer_loss.append(float(loss[-1].item()))
