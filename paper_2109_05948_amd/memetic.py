@@ -73,6 +73,16 @@ def prediction_quality(pred: torch.Tensor, actual: torch.Tensor, mean: float, sd
     return r, rel
 
 
+def wvcp_targets(f: torch.Tensor):
+    """Training scores of a WVCP generation: a search that met no legal
+    colouring (score 0x7fffffff) gets the generation's worst legal score;
+    None when no search met one."""
+    legal = f != 0x7FFFFFFF
+    if not bool(legal.any()):
+        return None
+    return torch.where(legal, f, f[legal].max())
+
+
 def _score_scale(f: torch.Tensor) -> tuple:
     """Mean and population standard deviation, as dlm_standardize takes them."""
     d = f.double()
@@ -188,10 +198,13 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         ind_next += nsel
         if learned:
             res.predictions.append((gen,) + prediction_quality(scores[idx.long()], f_off, *scale))
-            scale = _score_scale(f_off)
-            tgt = A.standardize(f_off)
-            loss = sc.train(start, tgt, batch=batch, epochs=epochs, lr=lr)
-            res.scorer_loss.append(float(loss[-1].item()))
+            f_t = wvcp_targets(f_off) if weighted else f_off
+            if f_t is not None:
+                scale = _score_scale(f_t)
+                loss = sc.train(start, A.standardize(f_t), batch=batch, epochs=epochs, lr=lr)
+                res.scorer_loss.append(float(loss[-1].item()))
+            else:
+                res.scorer_loss.append(float("nan"))
         if diversity:
             pool, nxt = pools
             A.partition_distance(cols, k, off, out=pool[:pop, pop:])

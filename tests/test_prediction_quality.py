@@ -1,6 +1,7 @@
-"""Host-side measures of the network's prediction quality (the paper's
-analysis of its network, Section 4.2): Pearson correlation and median
-relative error, checked on hand-made cases."""
+"""Host-side logic of the learned loop, checked on hand-made cases: the
+measures of the network's prediction quality (the paper's analysis of its
+network, Section 4.2: Pearson correlation and median relative error) and
+the WVCP training scores of searches without a legal colouring."""
 import math
 
 import torch
@@ -40,3 +41,11 @@ def test_degenerate_cases_give_nan():
     actual = torch.tensor([1, 2, 3], dtype=torch.int32)
     assert all(math.isnan(x) for x in prediction_quality(torch.zeros(3), actual, 2.0, 1.0))
     assert all(math.isnan(x) for x in prediction_quality(torch.zeros(1), actual[:1], 2.0, 1.0))
+
+
+def test_wvcp_targets():
+    from paper_2109_05948_amd.memetic import wvcp_targets
+    f = torch.tensor([120, 0x7FFFFFFF, 90, 0x7FFFFFFF], dtype=torch.int32)
+    assert wvcp_targets(f).tolist() == [120, 120, 90, 120]
+    assert wvcp_targets(torch.tensor([7, 5], dtype=torch.int32)).tolist() == [7, 5]
+    assert wvcp_targets(torch.full((3,), 0x7FFFFFFF, dtype=torch.int32)) is None
