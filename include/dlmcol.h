@@ -505,6 +505,10 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767, max_batch <= 65535,
  * max_batch k < 2^31.
  * ---------------------------------------------------------------------- */
+/* Calls on one network share its activation buffers and rocBLAS handle: they
+ * must not overlap (one stream, or ordered by the caller).  Errors return a
+ * negative code with a message from dlm_last_error(); device buffers belong
+ * to the caller, the network owns its own memory until dlm_invnet_destroy. */
 typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, rocBLAS handle */
 
 int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, const float* params_host,
