@@ -134,3 +134,37 @@ def test_first_layer_mixing_is_constant(setup):
     P, colors, k = setup
     x = inv.one_hot(colors, k)
     assert np.allclose(x.mean(axis=1), 1.0 / k)
+
+
+def test_operand_hook_reaches_both_operands_of_every_product():
+    """The operand hook (used to measure the parity tolerance) scales both
+    operands of each product: with q = multiplication by c, a one-layer
+    network's output moves to beta + c^2 (f - beta), its Lambda and Gamma
+    gradients scale by c^2; in a deeper network in evaluation mode the
+    first layer's products scale by c^2 as well."""
+    n, k, b, c = 9, 3, 5, 1.5
+    rng = np.random.default_rng(8)
+    colors = rng.integers(0, k, size=(b, n))
+    P = inv.init_params(n, [1], seed=9)
+    q = lambda a: c * np.asarray(a)  # noqa: E731
+    f, cache = inv.forward(P, colors, k, train=True)
+    fq, cacheq = inv.forward(P, colors, k, train=True, q=q)
+    beta = P["b0"][0]
+    assert np.allclose(fq - beta, c * c * (f - beta), rtol=1e-12, atol=1e-14)
+    df = rng.normal(size=b)
+    g = inv.backward(P, cache, df, k)
+    gq = inv.backward(P, cacheq, df, k, q=q)
+    for nm in ("L0", "G0"):
+        assert np.allclose(gq[nm], c * c * g[nm], rtol=1e-12, atol=1e-14), nm
+    assert np.allclose(gq["b0"], g["b0"], rtol=1e-12)  # the bias is no product
+    # deeper network, evaluation: the first layer's pre-normalisation values
+    P2 = inv.init_params(n, [4, 1], seed=10)
+    _, c0 = inv.forward(P2, colors, k, train=False)
+    _, c1 = inv.forward(P2, colors, k, train=False, q=q)
+    # zhat = (z + b - rm) / std with rm = 0 and rv = 1 at initialisation, so
+    # zhat * std - b is the sum of the two products
+    std = np.sqrt(1.0 + inv.BN_EPS)
+    prod0 = c0["zhat"][0] * std - P2["b0"]
+    prod1 = c1["zhat"][0] * std - P2["b0"]
+    assert np.abs(prod0).max() > 1e-3
+    assert np.allclose(prod1, c * c * prod0, rtol=1e-12, atol=1e-14)
