@@ -155,6 +155,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=0,
                     help="memetic1000: training epochs per generation (default: the workload's)")
     ap.add_argument("--generations", type=int, default=16, help="predict: generations per loop")
+    ap.add_argument("--eval-chunk", type=int, default=2048, help="invnet: colourings per evaluation pass")
     ap.add_argument("--tune", type=int, default=1,
                     help="invnet: choose the GEMM solutions by measurement before timing (1) or keep the "
                          "library's defaults (0)")
@@ -643,7 +644,7 @@ def bench_invnet(args, w, dlm, torch):
     """The paper's colour-invariant network for k-COL at the G(500, 0.5),
     k = 49 shape (hidden widths 10n, 5n, 2n x 5, n, n // 2; 44.3 M
     trainables): one generation's scoring of 8192 colourings (evaluation, in
-    chunks of 512) and one training epoch over 8192 (colouring, score) pairs
+    chunks of --eval-chunk, 2048 by default) and one training epoch over 8192 (colouring, score) pairs
     at the paper's batch of 100 (82 Adam steps).  Inputs are Philox-random
     colourings and standard-normal targets, resident before timing; weights
     from the seeded fully connected initialisation.
@@ -655,7 +656,7 @@ def bench_invnet(args, w, dlm, torch):
     g, k = w.graphs[0], w.k[0]
     n, p = g.n, args.pop or w.pop
     widths = col_widths(n)
-    batch, chunk = 100, 512
+    batch, chunk = 100, args.eval_chunk
     G = dlm.Graph.from_csr(g)
     net = dlm.InvNet(n, k, widths, invnet_weights(n, widths, seed=0), max_batch=chunk)
     col, _ = dlm.init_population(G, k, p, seed=31)

@@ -535,22 +535,60 @@ __global__ __launch_bounds__(256) void inv_bwd_apply_kernel(const float* __restr
   }
 }
 
-// Adam on one layer's trainables (Lambda, Gamma, beta[, gamma, mu], packed);
-// the first nb of them (Lambda and Gamma) also refresh their BF16 copy
-__global__ __launch_bounds__(256) void inv_adam_kernel(float* __restrict__ P, float* __restrict__ m,
-                                                       float* __restrict__ v, const float* __restrict__ g, int64_t total,
+// Where each layer's trainables start in the packed FP32 array, where its
+// Lambda and Gamma end (beta follows them), and where their BF16 copy starts
+constexpr int kMaxLayers = 64;
+struct inv_layout {
+  int64_t start[kMaxLayers + 1];  // start[nl] = total
+  int64_t lg_end[kMaxLayers];
+  int64_t bf[kMaxLayers];
+  int32_t nl;
+};
+
+__device__ __forceinline__ float adam_one(float p, float& m, float& v, float g, float lr, float bc1, float bc2) {
+  m = 0.9f * m + 0.1f * g;
+  v = 0.999f * v + 0.001f * g * g;
+  return p - lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+}
+
+// Adam over all trainables, four consecutive values per thread (16-byte
+// accesses; the array is 256-byte aligned); a value of some Lambda or Gamma
+// also refreshes its BF16 copy
+__global__ __launch_bounds__(256) void inv_adam_kernel(float* __restrict__ P, float* __restrict__ M,
+                                                       float* __restrict__ V, const float* __restrict__ G, int64_t total,
                                                        float lr, float bc1, float bc2, uint16_t* __restrict__ pb,
-                                                       int64_t nb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  const float gg = g[e];
-  const float mm = 0.9f * m[e] + 0.1f * gg;
-  const float vv = 0.999f * v[e] + 0.001f * gg * gg;
-  m[e] = mm;
-  v[e] = vv;
-  const float p = P[e] - lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
-  P[e] = p;
-  if (e < nb) pb[e] = to_bf16(p);
+                                                       const inv_layout lay) {
+  const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (e0 >= total) return;
+  float p[4], m[4], v[4], g[4];
+  const int cnt = total - e0 >= 4 ? 4 : (int)(total - e0);
+  if (cnt == 4) {
+    const float4 tp = *reinterpret_cast<const float4*>(P + e0), tm = *reinterpret_cast<const float4*>(M + e0),
+                 tv = *reinterpret_cast<const float4*>(V + e0), tg = *reinterpret_cast<const float4*>(G + e0);
+    p[0] = tp.x, p[1] = tp.y, p[2] = tp.z, p[3] = tp.w;
+    m[0] = tm.x, m[1] = tm.y, m[2] = tm.z, m[3] = tm.w;
+    v[0] = tv.x, v[1] = tv.y, v[2] = tv.z, v[3] = tv.w;
+    g[0] = tg.x, g[1] = tg.y, g[2] = tg.z, g[3] = tg.w;
+  } else {
+    for (int q = 0; q < cnt; ++q) p[q] = P[e0 + q], m[q] = M[e0 + q], v[q] = V[e0 + q], g[q] = G[e0 + q];
+  }
+  int j = 0;
+  while (j + 1 < lay.nl && lay.start[j + 1] <= e0) ++j;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q >= cnt) break;
+    const int64_t e = e0 + q;
+    while (j + 1 < lay.nl && lay.start[j + 1] <= e) ++j;
+    p[q] = adam_one(p[q], m[q], v[q], g[q], lr, bc1, bc2);
+    if (e < lay.lg_end[j]) pb[lay.bf[j] + (e - lay.start[j])] = to_bf16(p[q]);
+  }
+  if (cnt == 4) {
+    *reinterpret_cast<float4*>(P + e0) = make_float4(p[0], p[1], p[2], p[3]);
+    *reinterpret_cast<float4*>(M + e0) = make_float4(m[0], m[1], m[2], m[3]);
+    *reinterpret_cast<float4*>(V + e0) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    for (int q = 0; q < cnt; ++q) P[e0 + q] = p[q], M[e0 + q] = m[q], V[e0 + q] = v[q];
+  }
 }
 
 __global__ __launch_bounds__(256) void inv_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
@@ -569,6 +607,7 @@ struct dlm_invnet {
   // packed FP32 trainables per layer: L, G, beta, then gamma, mu (hidden layers)
   std::vector<int64_t> oL, oG, ob, og, om, oLb, oGb, orm, orv;
   std::vector<int> vw;  // vector width of each hidden layer's per-colouring kernels
+  inv_layout layout;    // the packed trainables, for the Adam kernel
   int64_t total = 0, nrun = 0;
   float *P = nullptr, *M = nullptr, *V = nullptr, *Gr = nullptr, *run = nullptr;
   uint16_t* Pb = nullptr;  // BF16 copies of every L and G
@@ -848,6 +887,13 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
   }
   s->total = o;
   s->nrun = orun;
+  s->layout.nl = nl;
+  for (int j = 0; j < nl; ++j) {
+    s->layout.start[j] = s->oL[j];
+    s->layout.lg_end[j] = s->ob[j];  // Lambda and Gamma precede beta
+    s->layout.bf[j] = s->oLb[j];
+  }
+  s->layout.start[nl] = o;
   // vector width per hidden layer: the widest of 4, 2, 1 that divides the
   // width and every packed offset the per-colouring kernels read or write
   // (activation buffers are 256-byte aligned and their rows l values long)
@@ -994,11 +1040,8 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets,
       if (rc != DLM_OK) break;
       ++s->adam_t;
       const float bc1 = 1.f - powf(0.9f, (float)s->adam_t), bc2 = 1.f - powf(0.999f, (float)s->adam_t);
-      for (int j = 0; j < s->nl; ++j) {  // one layer's trainables are contiguous
-        const int64_t o = s->oL[j], cnt = (j + 1 < s->nl ? s->oL[j + 1] : s->total) - o;
-        hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks(cnt)), dim3(256), 0, st, s->P + o, s->M + o, s->V + o,
-                           s->Gr + o, cnt, lr, bc1, bc2, s->Pb + s->oLb[j], 2 * (int64_t)s->lin[j] * s->lout[j]);
-      }
+      hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks((s->total + 3) / 4)), dim3(256), 0, st, s->P, s->M, s->V,
+                         s->Gr, s->total, lr, bc1, bc2, s->Pb, s->layout);
       DLM_HIP(hipGetLastError());
       ++step;
     }

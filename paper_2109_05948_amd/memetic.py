@@ -95,7 +95,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         epochs: int = 5, lr: float = 1e-3, block: int = 0, table: str = "auto",
         log=None, diversity: bool = False, neighbours: int = 16,
         init_colors: torch.Tensor | None = None, weighted: bool = False, rounds: int = 10,
-        target: int | None = None, network: str = "mlp", eval_chunk: int = 256,
+        target: int | None = None, network: str = "mlp", eval_chunk: int = 1024,
         tune_gemms: bool = False) -> MemeticResult:
     """One loop of Algorithm 1.  With ``weighted`` it solves the WVCP
     (Section 2.2): the start is the greedy colouring (k = 0 takes the largest
