@@ -628,15 +628,20 @@ struct dlm_invnet {
   std::map<std::tuple<int, int, int, int, int>, int32_t> solution;
   bool tuning = false;
   hipStream_t tune_stream = nullptr;
+  // the class-mean products (one row per colouring) run on a second stream,
+  // beside the class-row products of the same layer
+  hipStream_t side = nullptr;
+  rocblas_handle h_side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
 
-rocblas_status gemm_call(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+rocblas_status gemm_call(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
                          const void* A, int lda, const void* B, int ldb, float beta, float* C, int ldc,
                          int32_t sol) {
   const float alpha = 1.f;
-  return rocblas_gemm_ex(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r,
+  return rocblas_gemm_ex(h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r,
                          ldb, &beta, C, rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc,
                          rocblas_datatype_f32_r, sol >= 0 ? rocblas_gemm_algo_solution_index : rocblas_gemm_algo_standard,
                          sol >= 0 ? sol : 0, 0);
@@ -671,12 +676,12 @@ int tune_gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, 
   float best = 1e30f;
   int32_t pick = -1;
   for (int32_t sol : list) {
-    if (gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) != rocblas_status_success) continue;
+    if (gemm_call(s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) != rocblas_status_success) continue;
     constexpr int kReps = 3;
     (void)hipEventRecord(e0, s->tune_stream);
     bool ok = true;
     for (int r = 0; r < kReps && ok; ++r)
-      ok = gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) == rocblas_status_success;
+      ok = gemm_call(s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) == rocblas_status_success;
     (void)hipEventRecord(e1, s->tune_stream);
     if (hipEventSynchronize(e1) != hipSuccess) {
       (void)hipEventDestroy(e0);
@@ -695,29 +700,47 @@ int tune_gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, 
   return DLM_OK;
 }
 
-int gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A, int lda,
-         const void* B, int ldb, float beta, float* C, int ldc) {
+// side: issue on the second stream (a class-mean product)
+int gemm(dlm_invnet* s, bool side, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A,
+         int lda, const void* B, int ldb, float beta, float* C, int ldc) {
   if (s->tuning) return tune_gemm(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc);
   const auto it = s->solution.find(std::make_tuple((int)ta, (int)tb, m, n, k));
   const int32_t sol = it == s->solution.end() ? -1 : it->second;
-  const rocblas_status st = gemm_call(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol);
+  const rocblas_status st = gemm_call(side ? s->h_side : s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol);
   if (st != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_gemm_ex failed (%d)", (int)st);
   return DLM_OK;
 }
 
 // row-major C[rows][cols] = A[rows][inner] W[inner][cols]  (column-major: C^T = W^T A^T)
-int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, int rows, int inner, int cols, float* C) {
-  return gemm(s, rocblas_operation_none, rocblas_operation_none, cols, rows, inner, W, cols, A, inner, 0.f, C, cols);
-}
-// row-major C[inner][cols] = A[rows][inner]^T D[rows][cols]
-int mm_at(dlm_invnet* s, const uint16_t* A, const uint16_t* D, int rows, int inner, int cols, float* C) {
-  return gemm(s, rocblas_operation_none, rocblas_operation_transpose, cols, inner, rows, D, cols, A, inner, 0.f, C,
+int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, int rows, int inner, int cols, float* C,
+            bool side = false) {
+  return gemm(s, side, rocblas_operation_none, rocblas_operation_none, cols, rows, inner, W, cols, A, inner, 0.f, C,
               cols);
 }
+// row-major C[inner][cols] = A[rows][inner]^T D[rows][cols]
+int mm_at(dlm_invnet* s, const uint16_t* A, const uint16_t* D, int rows, int inner, int cols, float* C,
+          bool side = false) {
+  return gemm(s, side, rocblas_operation_none, rocblas_operation_transpose, cols, inner, rows, D, cols, A, inner, 0.f,
+              C, cols);
+}
 // row-major C[rows][inner] = D[rows][cols] W[inner][cols]^T
-int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inner, int cols, float* C) {
-  return gemm(s, rocblas_operation_transpose, rocblas_operation_none, inner, rows, cols, W, cols, D, cols, 0.f, C,
-              inner);
+int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inner, int cols, float* C,
+          bool side = false) {
+  return gemm(s, side, rocblas_operation_transpose, rocblas_operation_none, inner, rows, cols, W, cols, D, cols, 0.f,
+              C, inner);
+}
+
+// the side stream starts after everything issued on st so far; st later
+// waits for everything issued on the side stream so far
+int fork_side(dlm_invnet* s, hipStream_t st) {
+  DLM_HIP(hipEventRecord(s->ev_fork, st));
+  DLM_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+  return DLM_OK;
+}
+int join_side(dlm_invnet* s, hipStream_t st) {
+  DLM_HIP(hipEventRecord(s->ev_join, s->side));
+  DLM_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  return DLM_OK;
 }
 
 unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
@@ -754,8 +777,10 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
                          s->P + s->oG[j], s->P + s->ob[j], k, li, s->fout);
       break;
     }
-    int rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
-    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
+    int rc = fork_side(s, st);
+    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j], true);
+    if (rc == DLM_OK) rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
+    if (rc == DLM_OK) rc = join_side(s, st);
     if (rc != DLM_OK) return rc;
     const float* mean = s->run + s->orm[j];
     const float* var = s->run + s->orv[j];
@@ -790,13 +815,14 @@ int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStr
       hipLaunchKernelGGL(inv_out_dx_kernel, tiles, dim3(256), 0, st, s->df, s->P + s->oL[j], s->P + s->oG[j], k, li,
                          s->dX, s->dR);
     } else {
-      int rc = mm_at(s, s->X[j], s->dZb, (int)N, li, lo, s->Gr + s->oL[j]);
-      if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
+      int rc = fork_side(s, st);
+      if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j], true);
+      if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR, true);
+      if (rc == DLM_OK) rc = mm_at(s, s->X[j], s->dZb, (int)N, li, lo, s->Gr + s->oL[j]);
+      if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], (int)N, li, lo, s->dX);
+      if (rc == DLM_OK) rc = join_side(s, st);
       if (rc != DLM_OK) return rc;
       if (j == 0) break;
-      rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], (int)N, li, lo, s->dX);
-      if (rc == DLM_OK) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
-      if (rc != DLM_OK) return rc;
     }
     // through LReLU and the normalisation of layer j - 1 (width li)
     const int p = j - 1;
@@ -959,6 +985,14 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
     delete s;
     return set_error(DLM_E_HIP, "rocblas_create_handle failed");
   }
+  if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess ||
+      rocblas_create_handle(&s->h_side) != rocblas_status_success ||
+      rocblas_set_stream(s->h_side, s->side) != rocblas_status_success) {
+    dlm_invnet_destroy(s);
+    return set_error(DLM_E_HIP, "dlm_invnet_create: second stream set-up failed");
+  }
   // host parameters: the trainables, then the running estimates
   int rc = DLM_OK;
   if (hipMemcpy(s->P, params_host, 4 * o, hipMemcpyHostToDevice) != hipSuccess ||
@@ -968,9 +1002,7 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
   if (rc == DLM_OK) rc = inv_refresh_bf16(s, nullptr);
   if (rc == DLM_OK && hipDeviceSynchronize() != hipSuccess) rc = set_error(DLM_E_HIP, "dlm_invnet_create: sync");
   if (rc != DLM_OK) {
-    rocblas_destroy_handle(s->h);
-    (void)hipFree(s->ws);
-    delete s;
+    dlm_invnet_destroy(s);
     return rc;
   }
   *out = s;
@@ -979,7 +1011,12 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
 
 int dlm_invnet_destroy(dlm_invnet* s) {
   if (!s) return DLM_OK;
-  rocblas_destroy_handle(s->h);
+  if (s->side) (void)hipStreamSynchronize(s->side);
+  if (s->h_side) rocblas_destroy_handle(s->h_side);
+  if (s->h) rocblas_destroy_handle(s->h);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
   (void)hipFree(s->ws);
   delete s;
   return DLM_OK;
