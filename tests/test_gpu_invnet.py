@@ -338,3 +338,53 @@ def test_tuned_products(dlm, dev):
     dg = deviation(run, wg)
     for nm in ("L0", "G0", "L1", "G1", "L2", "G2", "L3", "G3", "g0", "m0", "g1", "m1"):
         close(g[nm], wg[nm], dg[nm], nm)
+
+
+def test_edge_cases(dlm, dev):
+    """Empty evaluation, zero epochs, a gradient batch of one colouring (the
+    normalisation then runs over its k class rows only), and training data
+    shorter than one batch."""
+    n, k, widths = 50, 6, [40, 24, 1]
+    P = f32(params(n, widths, 31))
+    rng = np.random.default_rng(32)
+    colors = rng.integers(0, k, size=(5, n)).astype(np.int16)
+    targets = rng.normal(0, 1, size=5).astype(np.float32)
+    say("invnet edge cases")
+    net = dlm.InvNet(n, k, widths, P, max_batch=8)
+    out = net.forward(cuda(colors[:0]))
+    assert out.shape == (0,)
+    before = net.params()
+    assert net.train(cuda(colors), cuda(targets), batch=8, epochs=0).shape == (0,)
+    after = net.params()
+    assert all(np.array_equal(before[nm], after[nm]) for nm in before)
+    # one colouring per batch
+    g, loss = net.grad(cuda(colors[:1]), cuda(targets[:1]))
+    g = net.unpack(g.cpu().numpy(), net.train_names)
+
+    def run(q):
+        f, cache = ref.forward(P, colors[:1], k, train=True, q=q)
+        out = ref.backward(P, cache, 2.0 * (f - targets[:1]), k, q=q)
+        out["loss"] = np.mean((f - targets[:1]) ** 2)
+        return out
+
+    want = run(None)
+    dv = deviation(run, want)
+    close(loss.cpu().numpy(), want["loss"], dv["loss"], "loss")
+    for nm in ("L0", "L1", "L2", "G2", "g0", "m0", "g1", "m1"):
+        close(g[nm], want[nm], dv[nm], nm)
+    # with one colouring every row of a hidden layer's batch shares the class
+    # mean, so the normalisation removes that path too: the hidden layers'
+    # Gamma gradients are zero up to FP32 round-off (as their biases are)
+    scale = max(np.abs(want[nm]).max() for nm in net.train_names)
+    for nm in ("G0", "G1", "b0", "b1"):
+        assert np.abs(want[nm]).max() <= 1e-12 * scale and np.abs(g[nm]).max() <= 1e-4 * scale, nm
+    # five pairs with a batch of eight: one step over all five
+    losses = net.train(cuda(colors), cuda(targets), batch=8, epochs=2).cpu().numpy()
+    assert losses.shape == (2,) and np.isfinite(losses).all()
+
+    def first_loss(q):  # the first step's loss: a training-mode pass over the five
+        f, _ = ref.forward(P, colors, k, train=True, q=q)
+        return {"loss": np.mean((f - targets) ** 2)}
+
+    want1 = first_loss(None)
+    close(losses[:1], np.array([want1["loss"]]), deviation(first_loss, want1)["loss"], "first loss")
