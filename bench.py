@@ -156,9 +156,9 @@ def main():
                     help="memetic1000: training epochs per generation (default: the workload's)")
     ap.add_argument("--generations", type=int, default=16, help="predict: generations per loop")
     ap.add_argument("--eval-chunk", type=int, default=2048, help="invnet: colourings per evaluation pass")
-    ap.add_argument("--tune", type=int, default=1,
-                    help="invnet: choose the GEMM solutions by measurement before timing (1) or keep the "
-                         "library's defaults (0)")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="invnet, predict, memetic1000: choose the GEMM solutions of the colour-invariant "
+                         "network by measurement before timing (1) or keep the library's defaults (0)")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
