@@ -291,7 +291,9 @@ def test_paper_depth_sampled(dlm, dev):
     """The k-COL network of the paper for n = 500 (hidden widths 10n, 5n,
     2n x 5, n, n // 2), k = 49: 200 colourings evaluated in chunks of 100,
     four of them checked against the oracle one by one; one training batch of
-    100 gives a finite loss and leaves the running estimates finite."""
+    100 gives a finite loss and leaves the running estimates finite; and
+    2100 colourings evaluated in the benchmark's chunks of 2048, five
+    checked against the oracle."""
     n, k = 500, 49
     widths = [10 * n, 5 * n] + [2 * n] * 5 + [n, n // 2, 1]
     rng = np.random.default_rng(7)
@@ -309,6 +311,18 @@ def test_paper_depth_sampled(dlm, dev):
     assert np.isfinite(losses).all()
     after = net.params()
     assert all(np.isfinite(after[nm]).all() for nm in net.run_names)
+    del net
+    # the benchmark's evaluation pass: chunks of 2048 colourings (100,352 class
+    # rows per product), 2100 colourings so the second chunk is ragged
+    big = rng.integers(0, k, size=(2100, n)).astype(np.int16)
+    big[:200] = colors
+    say("invnet paper depth, chunks of 2048")
+    net = dlm.InvNet(n, k, widths, P, max_batch=2048)
+    got = net.forward(cuda(big)).cpu().numpy()
+    idx = [0, 99, 2047, 2048, 2099]
+    want, _ = ref.forward(P, big[idx], k, train=False)
+    dv = deviation(lambda q: {"f": ref.forward(P, big[idx], k, train=False, q=q)[0]}, {"f": want})
+    close(got[idx], want, dv["f"], "paper depth, chunks of 2048")
 
 
 def test_tuned_products(dlm, dev):
