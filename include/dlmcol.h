@@ -505,8 +505,11 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767, max_batch <= 65535,
  * max_batch k < 2^31.
  * ---------------------------------------------------------------------- */
-/* Calls on one network share its activation buffers and rocBLAS handle: they
- * must not overlap (one stream, or ordered by the caller).  Errors return a
+/* Calls on one network share its activation buffers and rocBLAS handles:
+ * they must not overlap (one stream, or ordered by the caller).  Each call
+ * is ordered on the stream it is given: the network's second stream forks
+ * from it and joins it again before the call returns.  Use a network on the
+ * device that was current at its creation.  Errors return a
  * negative code with a message from dlm_last_error(); device buffers belong
  * to the caller, the network owns its own memory until dlm_invnet_destroy. */
 typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, rocBLAS handle */
