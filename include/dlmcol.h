@@ -30,7 +30,7 @@
 extern "C" {
 #endif
 
-#define DLM_ABI_VERSION 1
+#define DLM_ABI_VERSION 2
 
 #define DLM_OK 0
 #define DLM_E_INVAL (-1)       /* bad argument (null pointer, size, range, CSR rule) */
@@ -53,6 +53,8 @@ const char* dlm_last_error(void);
  * ---------------------------------------------------------------------- */
 typedef struct dlm_graph dlm_graph; /* opaque, immutable after creation */
 
+#define DLM_G_BITSET 0x1u /* also keep bitset adjacency rows: not built (DLM_E_UNSUPPORTED) */
+
 /*
  * Validate and upload an undirected simple graph in CSR form.
  *   n            number of vertices, 1 <= n <= 32767
@@ -60,12 +62,21 @@ typedef struct dlm_graph dlm_graph; /* opaque, immutable after creation */
  *   col_idx_host int32[row_ptr[n]]: both directions of every edge, each row
  *                strictly ascending, indices in [0, n), no self loops,
  *                symmetric
- *   weights_host int32[n] vertex weights w_v > 0 (weighted problem), or NULL
- * On success *out owns device copies; release with dlm_graph_destroy.
- * Errors: DLM_E_INVAL for any CSR rule broken, DLM_E_NOMEM, DLM_E_HIP.
+ *   weights_host int32[n] vertex weights w_v > 0 (weighted problem), or NULL;
+ *                a weighted graph also stores the greedy start order of
+ *                Section 2.1 (weight descending, degree descending, index
+ *                ascending), computed here once
+ *   flags        0, or DLM_G_BITSET (returns DLM_E_UNSUPPORTED: this library
+ *                streams CSR rows only); other bits are DLM_E_INVAL
+ *   stream       the uploads are ordered on it; the call synchronises it
+ *                before returning, so the host arrays may be freed at once
+ * On success *out owns device copies (allocated on the current device, which
+ * every later call on the graph must use); release with dlm_graph_destroy.
+ * Errors: DLM_E_INVAL for any CSR rule broken, DLM_E_UNSUPPORTED,
+ * DLM_E_NOMEM, DLM_E_HIP.
  */
 int dlm_graph_create(int32_t n, const int32_t* row_ptr_host, const int32_t* col_idx_host,
-                     const int32_t* weights_host, dlm_graph** out);
+                     const int32_t* weights_host, uint32_t flags, void* stream, dlm_graph** out);
 int dlm_graph_destroy(dlm_graph* g);
 /* n, number of CSR entries (2|E|) and the maximum degree; any output may be NULL. */
 int dlm_graph_info(const dlm_graph* g, int32_t* n, int64_t* nnz, int32_t* max_deg);
@@ -133,6 +144,17 @@ typedef struct dlm_tabu_params {
 } dlm_tabu_params;
 
 /*
+ * Device workspace a dlm_tabu_batch call with these arguments needs, in
+ * bytes (0 for the LDS tiers).  The automatic table and block are resolved
+ * as the call resolves them, on the current device.  The device-memory tiers
+ * need their tables (pop * (n + 1) * kp entries of 4 bytes for GLOBAL16, 2
+ * for SPLIT16 and SPLIT8); SPLIT8 adds a copy of the start colourings and
+ * the rerun tables (at most 2 per CU and 1 GiB).
+ * Errors: as dlm_tabu_batch's argument checks.
+ */
+int dlm_tabu_workspace_bytes(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop, size_t* bytes);
+
+/*
  * Run TabuCol on every individual of a population.
  *   pop          number of individuals (0 is a no-op)
  *   colors_dev   int16[pop][n]: in = start colouring S^O, out = best S'
@@ -147,15 +169,21 @@ typedef struct dlm_tabu_params {
  *                v = c = 0xffff
  *   trace_dev    int32[pop][trace_cap][2] or NULL: {v | c << 16, f_after} of
  *                the first trace_cap iterations
+ *   workspace_dev, workspace_bytes  caller-owned device scratch, 256-byte
+ *                aligned, at least dlm_tabu_workspace_bytes(g, p, pop) bytes
+ *                (may be NULL when that is 0); its contents on entry do not
+ *                matter, and it must not be shared with a call that overlaps
+ *                this one.  The call allocates no device memory.
  * A start colouring holding a colour outside [0, k) is left untouched and its
  * individual gets f_best = iters = -1 (its stats and hash are not written).
- * Errors: DLM_E_INVAL (arguments),
- * DLM_E_UNSUPPORTED (table does not fit the requested storage),
- * DLM_E_NOMEM (global table workspace), DLM_E_HIP.
+ * Errors: DLM_E_INVAL (arguments, workspace missing, too small or
+ * misaligned), DLM_E_UNSUPPORTED (table does not fit the requested storage),
+ * DLM_E_HIP.
  */
 int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
                    int16_t* colors_dev, int32_t* f_best_dev, int32_t* iters_dev,
-                   int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev, void* stream);
+                   int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev,
+                   void* workspace_dev, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Uneven batches: the populations of many graphs (any mix of n, k and

@@ -31,5 +31,6 @@ from ._abi import (  # noqa: F401
     invnet_names,
     lib,
     tabu_batch,
+    tabu_workspace_bytes,
     wvcp_batch,
 )

@@ -27,7 +27,7 @@ INIT_MODES = {"random": 0, "greedy": 1}
 
 EXPORTS = [
     "dlm_abi_version", "dlm_last_error", "dlm_graph_create", "dlm_graph_destroy", "dlm_graph_info",
-    "dlm_init_population", "dlm_tabu_batch", "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
+    "dlm_init_population", "dlm_tabu_workspace_bytes", "dlm_tabu_batch", "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
     "dlm_wvcp_batch", "dlm_scorer_create", "dlm_scorer_destroy", "dlm_scorer_num_params",
     "dlm_scorer_get_params", "dlm_score_offspring", "dlm_scorer_grad", "dlm_scorer_train",
     "dlm_gather_rows", "dlm_standardize", "dlm_random_pairs", "dlm_pop_update",
@@ -65,11 +65,12 @@ def lib():
             P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
             L.dlm_abi_version.restype = C.c_int
             L.dlm_last_error.restype = C.c_char_p
-            L.dlm_graph_create.argtypes = [I32, P, P, P, C.POINTER(P)]
+            L.dlm_graph_create.argtypes = [I32, P, P, P, C.c_uint32, P, C.POINTER(P)]
             L.dlm_graph_destroy.argtypes = [P]
             L.dlm_graph_info.argtypes = [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I32)]
             L.dlm_init_population.argtypes = [P, I32, I32, U64, I32, I32, P, P, P]
-            L.dlm_tabu_batch.argtypes = [P, C.POINTER(TabuParams), I32, P, P, P, P, P, P, P]
+            L.dlm_tabu_workspace_bytes.argtypes = [P, C.POINTER(TabuParams), I32, C.POINTER(C.c_size_t)]
+            L.dlm_tabu_batch.argtypes = [P, C.POINTER(TabuParams), I32, P, P, P, P, P, P, P, C.c_size_t, P]
             L.dlm_evaluate.argtypes = [P, I32, P, I32, P, P, P]
             L.dlm_gpx_batch.argtypes = [P, I32, P, I32, P, I32, I32, U64, C.c_uint32, P, P]
             L.dlm_select.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P, P]
@@ -145,12 +146,14 @@ def abi_version() -> int:
 class Graph:
     """dlm_graph: a validated CSR graph resident in device memory."""
 
-    def __init__(self, n: int, row_ptr, col_idx, weights=None):
+    def __init__(self, n: int, row_ptr, col_idx, weights=None, flags: int = 0, stream=None):
         rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
         ci = np.ascontiguousarray(col_idx, dtype=np.int32)
         w = None if weights is None else np.ascontiguousarray(weights, dtype=np.int32)
         h = C.c_void_p()
-        _check("dlm_graph_create", lib().dlm_graph_create(n, _ptr(rp), _ptr(ci), _ptr(w), C.byref(h)))
+        st = _stream(stream) if torch.cuda.is_available() else None
+        _check("dlm_graph_create", lib().dlm_graph_create(n, _ptr(rp), _ptr(ci), _ptr(w), flags, st,
+                                                          C.byref(h)))
         self._h = h
         self.n = int(n)
         self.weighted = w is not None
@@ -198,11 +201,32 @@ def init_population(graph: Graph, k: int, pop: int, seed: int, ind_base: int = 0
     return colors, k_used
 
 
+def _tabu_params(k, max_iters, seed, ind_base, ten_num, ten_den, ten_rand, block, table, trace_cap):
+    return TabuParams(k, max_iters, ten_num, ten_den, ten_rand, ind_base, seed & (2**64 - 1),
+                      block, TABLES[table], trace_cap, 0)
+
+
+def tabu_workspace_bytes(graph: Graph, pop: int, k: int, max_iters: int, seed: int = 0,
+                         ind_base: int = 0, ten_num: int = 6, ten_den: int = 10, ten_rand: int = 10,
+                         block: int = 0, table: str = "auto", trace_cap: int = 0) -> int:
+    """dlm_tabu_workspace_bytes: device scratch a dlm_tabu_batch call needs."""
+    prm = _tabu_params(k, max_iters, seed, ind_base, ten_num, ten_den, ten_rand, block, table, trace_cap)
+    out = C.c_size_t()
+    _check("dlm_tabu_workspace_bytes",
+           lib().dlm_tabu_workspace_bytes(graph.handle, C.byref(prm), pop, C.byref(out)))
+    return int(out.value)
+
+
 def tabu_batch(graph: Graph, colors: torch.Tensor, k: int, max_iters: int, seed: int,
                ind_base: int = 0, ten_num: int = 6, ten_den: int = 10, ten_rand: int = 10,
                block: int = 0, table: str = "auto", stats: bool = True, hashes: bool = True,
-               trace_cap: int = 0, out: dict | None = None, stream=None) -> dict:
-    """dlm_tabu_batch on every row of ``colors`` (modified in place to the best colouring)."""
+               trace_cap: int = 0, out: dict | None = None, workspace: torch.Tensor | None = None,
+               stream=None) -> dict:
+    """dlm_tabu_batch on every row of ``colors`` (modified in place to the best colouring).
+
+    The device workspace is a torch tensor: ``workspace`` if given (uint8, at
+    least dlm_tabu_workspace_bytes), else one taken from torch's allocator
+    for this call."""
     _dev(colors, torch.int16, "colors")
     pop = colors.shape[0]
     if colors.dim() != 2 or colors.shape[1] != graph.n:
@@ -216,12 +240,19 @@ def tabu_batch(graph: Graph, colors: torch.Tensor, k: int, max_iters: int, seed:
         o["hash"] = torch.empty(pop, dtype=torch.int64, device=dev) if hashes else None
         o["trace"] = (torch.empty((pop, trace_cap, 2), dtype=torch.int32, device=dev)
                       if trace_cap else None)
-    prm = TabuParams(k, max_iters, ten_num, ten_den, ten_rand, ind_base, seed & (2**64 - 1),
-                     block, TABLES[table], trace_cap, 0)
+    prm = _tabu_params(k, max_iters, seed, ind_base, ten_num, ten_den, ten_rand, block, table, trace_cap)
+    if workspace is None:
+        need = C.c_size_t()
+        _check("dlm_tabu_workspace_bytes",
+               lib().dlm_tabu_workspace_bytes(graph.handle, C.byref(prm), pop, C.byref(need)))
+        workspace = torch.empty(need.value, dtype=torch.uint8, device=dev) if need.value else None
+    if workspace is not None:
+        _dev(workspace, torch.uint8, "workspace")
+    ws_bytes = workspace.numel() if workspace is not None else 0
     _check("dlm_tabu_batch",
            lib().dlm_tabu_batch(graph.handle, C.byref(prm), pop, _ptr(colors), _ptr(o["f_best"]),
                                 _ptr(o["iters"]), _ptr(o.get("stats")), _ptr(o.get("hash")),
-                                _ptr(o.get("trace")), _stream(stream)))
+                                _ptr(o.get("trace")), _ptr(workspace), ws_bytes, _stream(stream)))
     o["colors"] = colors
     return o
 

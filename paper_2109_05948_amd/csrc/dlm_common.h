@@ -167,4 +167,5 @@ struct dlm_graph {
   int32_t* col_idx = nullptr;  // device int32[nnz]
   int32_t* erow = nullptr;     // device int32[nnz]: source vertex of each CSR entry
   int32_t* weights = nullptr;  // device int32[n] or null
+  int32_t* order = nullptr;    // device int32[n]: greedy WVCP vertex order (weighted graphs only)
 };

@@ -3,7 +3,9 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "dlm_common.h"
@@ -113,9 +115,12 @@ int dlm_abi_version(void) { return DLM_ABI_VERSION; }
 const char* dlm_last_error(void) { return g_last_error.c_str(); }
 
 int dlm_graph_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
-                     const int32_t* weights, dlm_graph** out) {
+                     const int32_t* weights, uint32_t flags, void* stream, dlm_graph** out) {
   if (!out) return set_error(DLM_E_INVAL, "dlm_graph_create: out is NULL");
   *out = nullptr;
+  if (flags & ~(uint32_t)DLM_G_BITSET) return set_error(DLM_E_INVAL, "dlm_graph_create: unknown flags 0x%x", flags);
+  if (flags & DLM_G_BITSET)
+    return set_error(DLM_E_UNSUPPORTED, "dlm_graph_create: bitset adjacency rows are not built by this library");
   if (n < 1 || n > 32767) return set_error(DLM_E_INVAL, "dlm_graph_create: n=%d outside [1, 32767]", n);
   if (!row_ptr) return set_error(DLM_E_INVAL, "dlm_graph_create: row_ptr is NULL");
   if (row_ptr[0] != 0) return set_error(DLM_E_INVAL, "dlm_graph_create: row_ptr[0] != 0");
@@ -168,33 +173,49 @@ int dlm_graph_create(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   if (weights && (int64_t)max_w * n > (1ll << 30))
     return set_error(DLM_E_UNSUPPORTED, "dlm_graph_create: n * max weight exceeds 2^30");
 
+  // greedy WVCP start (Section 2.1): vertices by weight descending, then
+  // degree descending, then index ascending; a property of the graph, so it
+  // is computed once here
+  std::vector<int32_t> order;
+  if (weights) {
+    order.resize((size_t)n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+      if (weights[a] != weights[b]) return weights[a] > weights[b];
+      const int32_t da = row_ptr[a + 1] - row_ptr[a], db = row_ptr[b + 1] - row_ptr[b];
+      if (da != db) return da > db;
+      return a < b;
+    });
+  }
+
   dlm_graph* g = new dlm_graph();
   g->n = n;
   g->nnz = nnz;
   g->max_deg = max_deg;
   g->max_w = max_w;
   (void)hipGetDevice(&g->device);
+  hipStream_t s = (hipStream_t)stream;
   auto fail = [&](hipError_t e, const char* what) {
+    (void)hipStreamSynchronize(s);  // no copy may still read or write g's buffers
     dlm_graph_destroy(g);
     return hip_fail(e, what);
   };
+  auto upload = [&](int32_t** dst, const int32_t* src, int64_t count) -> hipError_t {
+    hipError_t e = hipMalloc(dst, sizeof(int32_t) * (size_t)(count > 0 ? count : 1));
+    if (e == hipSuccess && count > 0)
+      e = hipMemcpyAsync(*dst, src, sizeof(int32_t) * (size_t)count, hipMemcpyHostToDevice, s);
+    return e;
+  };
   hipError_t e;
-  if ((e = hipMalloc(&g->row_ptr, sizeof(int32_t) * (n + 1))) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = hipMalloc(&g->col_idx, sizeof(int32_t) * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = hipMalloc(&g->erow, sizeof(int32_t) * (nnz > 0 ? nnz : 1))) != hipSuccess) return fail(e, "hipMalloc");
-  if ((e = hipMemcpy(g->row_ptr, row_ptr, sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
-    return fail(e, "hipMemcpy");
-  if (nnz > 0) {
-    if ((e = hipMemcpy(g->col_idx, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice)) != hipSuccess)
-      return fail(e, "hipMemcpy");
-    if ((e = hipMemcpy(g->erow, erow.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice)) != hipSuccess)
-      return fail(e, "hipMemcpy");
-  }
+  if ((e = upload(&g->row_ptr, row_ptr, n + 1)) != hipSuccess) return fail(e, "graph upload (row_ptr)");
+  if ((e = upload(&g->col_idx, col_idx, nnz)) != hipSuccess) return fail(e, "graph upload (col_idx)");
+  if ((e = upload(&g->erow, erow.data(), nnz)) != hipSuccess) return fail(e, "graph upload (erow)");
   if (weights) {
-    if ((e = hipMalloc(&g->weights, sizeof(int32_t) * n)) != hipSuccess) return fail(e, "hipMalloc");
-    if ((e = hipMemcpy(g->weights, weights, sizeof(int32_t) * n, hipMemcpyHostToDevice)) != hipSuccess)
-      return fail(e, "hipMemcpy");
+    if ((e = upload(&g->weights, weights, n)) != hipSuccess) return fail(e, "graph upload (weights)");
+    if ((e = upload(&g->order, order.data(), n)) != hipSuccess) return fail(e, "graph upload (order)");
   }
+  // the host arrays (the caller's and the local ones) are read synchronously
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(e, "hipStreamSynchronize");
   *out = g;
   return DLM_OK;
 }
@@ -205,6 +226,7 @@ int dlm_graph_destroy(dlm_graph* g) {
   (void)hipFree(g->col_idx);
   (void)hipFree(g->erow);
   (void)hipFree(g->weights);
+  (void)hipFree(g->order);
   delete g;
   return DLM_OK;
 }

@@ -110,28 +110,11 @@ extern "C" int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, u
   }
   if (mode != DLM_INIT_GREEDY) return set_error(DLM_E_INVAL, "dlm_init_population: unknown mode %d", mode);
   if (!g->weights) return set_error(DLM_E_INVAL, "dlm_init_population: greedy mode needs vertex weights");
-  // greedy order: weight descending, degree descending, index ascending
-  std::vector<int32_t> rp(g->n + 1), w(g->n);
-  DLM_HIP(hipMemcpy(rp.data(), g->row_ptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDeviceToHost));
-  DLM_HIP(hipMemcpy(w.data(), g->weights, sizeof(int32_t) * g->n, hipMemcpyDeviceToHost));
-  std::vector<int32_t> order(g->n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-    if (w[a] != w[b]) return w[a] > w[b];
-    const int32_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
-    if (da != db) return da > db;
-    return a < b;
-  });
-  int32_t* d_order = nullptr;
-  DLM_HIP(hipMallocAsync((void**)&d_order, sizeof(int32_t) * g->n, s));
-  DLM_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * g->n, hipMemcpyHostToDevice, s));
+  // the greedy order (weight descending, degree descending, index ascending)
+  // was computed when the graph was created
   const size_t lds = align16(2u * g->n) + 4u * ((g->n + 32) / 32 + 1);
-  hipLaunchKernelGGL(init_greedy_kernel, dim3(pop), dim3(256), lds, s, g->row_ptr, g->col_idx, d_order,
+  hipLaunchKernelGGL(init_greedy_kernel, dim3(pop), dim3(256), lds, s, g->row_ptr, g->col_idx, g->order,
                      g->n, make_key(seed), ind_base, colors, k_used);
-  hipError_t le = hipGetLastError();
-  // the order copy must finish before the host vector goes away
-  DLM_HIP(hipStreamSynchronize(s));
-  DLM_HIP(hipFreeAsync(d_order, s));
-  if (le != hipSuccess) return hip_fail(le, "init_greedy_kernel launch");
+  DLM_HIP(hipGetLastError());
   return DLM_OK;
 }

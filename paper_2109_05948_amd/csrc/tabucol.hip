@@ -126,30 +126,42 @@ static int launch_tab(const TabuArgs& a, int pop, int block, size_t lds, hipStre
   return set_error(DLM_E_INVAL, "dlm_tabu_batch: block=%d not in {64,128,256,512,1024}", block);
 }
 
-}  // namespace dlm
 
-using namespace dlm;
+// How a call runs: the table tier and block (AUTO resolved), the LDS of the
+// search (and rerun) kernel, and the caller-owned workspace it needs.
+struct TabuPlan {
+  int table = 0, block = 0;
+  uint64_t lds = 0, lds_rr = 0;
+  uint64_t gtab_bytes = 0;    // device-memory table part of every individual
+  uint64_t start_bytes = 0;   // SPLIT8: copy of the start colourings
+  uint64_t slot_bytes = 0;    // SPLIT8: one rerun slot (packed 16-bit table)
+  int64_t slots = 0;          // SPLIT8: rerun slots
+  uint64_t ws_bytes = 0;      // total, each part on a 256-byte boundary
+};
 
-extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
-                              int16_t* colors, int32_t* f_best, int32_t* iters, int64_t* stats,
-                              uint64_t* hash, int32_t* trace, void* stream) {
-  if (!g || !p) return set_error(DLM_E_INVAL, "dlm_tabu_batch: graph or params is NULL");
-  if (pop < 0) return set_error(DLM_E_INVAL, "dlm_tabu_batch: pop < 0");
-  if (p->k < 1 || p->k > 32767) return set_error(DLM_E_INVAL, "dlm_tabu_batch: k=%d outside [1, 32767]", p->k);
+static uint64_t align256(uint64_t x) { return (x + 255u) & ~255ull; }
+
+static int tabu_check(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop) {
+  if (!g || !p) return set_error(DLM_E_INVAL, "%s: graph or params is NULL", fn);
+  if (pop < 0) return set_error(DLM_E_INVAL, "%s: pop < 0", fn);
+  if (p->k < 1 || p->k > 32767) return set_error(DLM_E_INVAL, "%s: k=%d outside [1, 32767]", fn, p->k);
   if (p->max_iters < 0 || p->max_iters > (1 << 30))
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: max_iters=%d outside [0, 2^30]", p->max_iters);
+    return set_error(DLM_E_INVAL, "%s: max_iters=%d outside [0, 2^30]", fn, p->max_iters);
   if (p->ten_den <= 0 || p->ten_num < 0 || p->ten_num > 32767)
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: tenure slope %d/%d invalid", p->ten_num, p->ten_den);
+    return set_error(DLM_E_INVAL, "%s: tenure slope %d/%d invalid", fn, p->ten_num, p->ten_den);
   if (p->ten_rand < 1 || p->ten_rand > 1024)
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: ten_rand=%d outside [1, 1024]", p->ten_rand);
+    return set_error(DLM_E_INVAL, "%s: ten_rand=%d outside [1, 1024]", fn, p->ten_rand);
   if (p->ind_base < 0 || (int64_t)p->ind_base + pop > 0x7fffffffll)
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: ind_base + pop exceeds 2^31");
-  if (p->trace_cap < 0 || (p->trace_cap > 0 && !trace))
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: trace_cap=%d needs a trace buffer", p->trace_cap);
-  if (p->reserved != 0) return set_error(DLM_E_INVAL, "dlm_tabu_batch: reserved must be 0");
-  if (pop == 0) return DLM_OK;
-  if (!colors || !f_best || !iters) return set_error(DLM_E_INVAL, "dlm_tabu_batch: null output buffer");
+    return set_error(DLM_E_INVAL, "%s: ind_base + pop exceeds 2^31", fn);
+  if (p->trace_cap < 0) return set_error(DLM_E_INVAL, "%s: trace_cap=%d < 0", fn, p->trace_cap);
+  if (p->reserved != 0) return set_error(DLM_E_INVAL, "%s: reserved must be 0", fn);
+  return DLM_OK;
+}
+
+static int tabu_plan(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop, TabuPlan& P) {
   int block = p->block ? p->block : 256;
+  if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+    return set_error(DLM_E_INVAL, "%s: block=%d not in {64,128,256,512,1024}", fn, block);
   const int n = g->n, k = p->k;
   const int64_t lds_max = device_lds_limit();
   int table = p->table;
@@ -173,58 +185,82 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
     case DLM_TABLE_GLOBAL16: eb = 0; gb = TabGlobal16::kGlobalBytes; break;
     case DLM_TABLE_SPLIT16: eb = TabSplit16::kLdsBytes; gb = TabSplit16::kGlobalBytes; break;
     case DLM_TABLE_SPLIT8: eb = TabSplit8::kLdsBytes; gb = TabSplit8::kGlobalBytes; break;
-    default: return set_error(DLM_E_INVAL, "dlm_tabu_batch: unknown table %d", table);
+    default: return set_error(DLM_E_INVAL, "%s: unknown table %d", fn, table);
   }
-  const uint64_t lds = tabu_layout(n, k, nw, eb).bytes;
-  if (lds > (uint64_t)lds_max)
-    return set_error(DLM_E_UNSUPPORTED, "dlm_tabu_batch: %llu bytes of LDS needed, %lld available",
-                     (unsigned long long)lds, (long long)lds_max);
+  P.table = table;
+  P.block = block;
+  P.lds = tabu_layout(n, k, nw, eb).bytes;
+  if (P.lds > (uint64_t)lds_max)
+    return set_error(DLM_E_UNSUPPORTED, "%s: %llu bytes of LDS needed, %lld available", fn,
+                     (unsigned long long)P.lds, (long long)lds_max);
+  P.gtab_bytes = (uint64_t)pop * tab_entries(n, k) * (uint64_t)gb;
+  if (table == DLM_TABLE_SPLIT8 && pop > 0) {
+    // rerun slots: a few per CU, at most 1 GiB of packed tables
+    P.slot_bytes = tab_entries(n, k) * TabGlobal16::kGlobalBytes;
+    int64_t slots = std::min<int64_t>(pop, 2 * (int64_t)device_cu_count());
+    P.slots = std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)((1ull << 30) / std::max<uint64_t>(P.slot_bytes, 1))));
+    P.lds_rr = tabu_layout(n, k, nw, TabGlobal16::kLdsBytes).bytes;
+    P.start_bytes = sizeof(int16_t) * (uint64_t)pop * (uint64_t)n;
+  }
+  P.ws_bytes = align256(P.gtab_bytes) + align256(P.start_bytes) + align256(P.slot_bytes * (uint64_t)P.slots);
+  return DLM_OK;
+}
+
+}  // namespace dlm
+
+using namespace dlm;
+
+extern "C" int dlm_tabu_workspace_bytes(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                                        size_t* bytes) {
+  if (!bytes) return set_error(DLM_E_INVAL, "dlm_tabu_workspace_bytes: bytes is NULL");
+  *bytes = 0;
+  int rc = tabu_check("dlm_tabu_workspace_bytes", g, p, pop);
+  if (rc != DLM_OK) return rc;
+  TabuPlan P;
+  if ((rc = tabu_plan("dlm_tabu_workspace_bytes", g, p, pop, P)) != DLM_OK) return rc;
+  *bytes = (size_t)P.ws_bytes;
+  return DLM_OK;
+}
+
+extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                              int16_t* colors, int32_t* f_best, int32_t* iters, int64_t* stats,
+                              uint64_t* hash, int32_t* trace, void* workspace, size_t workspace_bytes,
+                              void* stream) {
+  int rc = tabu_check("dlm_tabu_batch", g, p, pop);
+  if (rc != DLM_OK) return rc;
+  if (p->trace_cap > 0 && !trace)
+    return set_error(DLM_E_INVAL, "dlm_tabu_batch: trace_cap=%d needs a trace buffer", p->trace_cap);
+  if (pop == 0) return DLM_OK;
+  if (!colors || !f_best || !iters) return set_error(DLM_E_INVAL, "dlm_tabu_batch: null output buffer");
+  TabuPlan P;
+  if ((rc = tabu_plan("dlm_tabu_batch", g, p, pop, P)) != DLM_OK) return rc;
+  if (P.ws_bytes > 0 && (!workspace || workspace_bytes < P.ws_bytes))
+    return set_error(DLM_E_INVAL, "dlm_tabu_batch: workspace of %zu bytes at %p, %llu needed (dlm_tabu_workspace_bytes)",
+                     workspace_bytes, workspace, (unsigned long long)P.ws_bytes);
+  if (P.ws_bytes > 0 && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+    return set_error(DLM_E_INVAL, "dlm_tabu_batch: workspace must be 256-byte aligned");
+  const int n = g->n, k = p->k;
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
   TabuArgs a{g->row_ptr, g->col_idx, g->erow, colors, f_best, iters, stats, hash, trace, nullptr,
              make_key(p->seed), n, k, p->max_iters, p->ten_num, p->ten_den, p->ten_rand,
              p->ind_base, p->trace_cap};
   hipStream_t s = (hipStream_t)stream;
-  if (table == DLM_TABLE_SPLIT8) {
-    // rerun slots: a few per CU, at most 1 GiB of packed tables
-    const uint64_t slot_bytes = tab_entries(n, k) * TabGlobal16::kGlobalBytes;
-    int64_t slots = std::min<int64_t>(pop, 2 * (int64_t)device_cu_count());
-    slots = std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)((1ull << 30) / std::max<uint64_t>(slot_bytes, 1))));
-    const size_t lds_rr = tabu_layout(n, k, nw, TabGlobal16::kLdsBytes).bytes;
-    const size_t bytes = (size_t)pop * tab_entries(n, k) * TabSplit8::kGlobalBytes;
-    const int64_t cells = (int64_t)pop * n;
-    int16_t* start = nullptr;
-    unsigned char* slot_mem = nullptr;
-    DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
-    hipError_t e = hipMallocAsync((void**)&start, sizeof(int16_t) * (size_t)cells, s);
-    if (e == hipSuccess) e = hipMallocAsync((void**)&slot_mem, (size_t)slots * slot_bytes, s);
-    int rc = e == hipSuccess ? DLM_OK : hip_fail(e, "hipMallocAsync");
-    if (rc == DLM_OK) {
+  if (P.gtab_bytes > 0) a.gtab = ws;
+  switch (P.table) {
+    case DLM_TABLE_SPLIT8: {
+      int16_t* start = reinterpret_cast<int16_t*>(ws + align256(P.gtab_bytes));
+      unsigned char* slot_mem = ws + align256(P.gtab_bytes) + align256(P.start_bytes);
+      const int64_t cells = (int64_t)pop * n;
       hipLaunchKernelGGL(copy_i16_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, colors, start,
                          cells);
-      const hipError_t le = hipGetLastError();
-      if (le != hipSuccess) rc = hip_fail(le, "copy_i16_kernel");
+      DLM_HIP(hipGetLastError());
+      if ((rc = launch_tab<TabSplit8>(a, pop, P.block, P.lds, s)) != DLM_OK) return rc;
+      const Rerun rr{start, slot_mem, (int32_t)P.slots};
+      return launch_tab<TabGlobal16>(a, pop, P.block, P.lds_rr, s, &rr);
     }
-    if (rc == DLM_OK) rc = launch_tab<TabSplit8>(a, pop, block, lds, s);
-    const Rerun rr{start, slot_mem, (int32_t)slots};
-    if (rc == DLM_OK) rc = launch_tab<TabGlobal16>(a, pop, block, lds_rr, s, &rr);
-    const hipError_t e1 = slot_mem ? hipFreeAsync(slot_mem, s) : hipSuccess;
-    const hipError_t e2 = start ? hipFreeAsync(start, s) : hipSuccess;
-    const hipError_t e3 = hipFreeAsync(a.gtab, s);
-    if (rc != DLM_OK) return rc;
-    DLM_HIP(e1);
-    DLM_HIP(e2);
-    DLM_HIP(e3);
-    return DLM_OK;
+    case DLM_TABLE_SPLIT16: return launch_tab<TabSplit16>(a, pop, P.block, P.lds, s);
+    case DLM_TABLE_GLOBAL16: return launch_tab<TabGlobal16>(a, pop, P.block, P.lds, s);
+    case DLM_TABLE_LDS32: return launch_tab<TabLds32>(a, pop, P.block, P.lds, s);
+    default: return launch_tab<TabLds16>(a, pop, P.block, P.lds, s);
   }
-  if (gb > 0) {
-    const size_t bytes = (size_t)pop * tab_entries(n, k) * gb;
-    DLM_HIP(hipMallocAsync((void**)&a.gtab, bytes, s));
-    int rc = table == DLM_TABLE_SPLIT16 ? launch_tab<TabSplit16>(a, pop, block, lds, s)
-                                        : launch_tab<TabGlobal16>(a, pop, block, lds, s);
-    hipError_t e = hipFreeAsync(a.gtab, s);
-    if (rc != DLM_OK) return rc;
-    DLM_HIP(e);
-    return DLM_OK;
-  }
-  if (table == DLM_TABLE_LDS32) return launch_tab<TabLds32>(a, pop, block, lds, s);
-  return launch_tab<TabLds16>(a, pop, block, lds, s);
 }

@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_version_and_error(L):
-    assert L.dlm_abi_version() == 1
+    assert L.dlm_abi_version() == 2
     assert isinstance(L.dlm_last_error(), bytes)
 
 
@@ -65,10 +65,27 @@ def test_graph_validation_rejects(L, case):
     assert len(L.dlm_last_error()) > 0
 
 
+def test_graph_flags(L):
+    """DLM_G_BITSET is declared but not built; unknown flag bits are invalid.
+    Both are rejected before any device work."""
+    rp = np.array([0, 1, 2], np.int32)
+    ci = np.array([1, 0], np.int32)
+    h = C.c_void_p()
+    P = C.c_void_p
+    assert L.dlm_graph_create(2, rp.ctypes.data_as(P), ci.ctypes.data_as(P), None, 0x1, None, C.byref(h)) == -4
+    assert b"bitset" in L.dlm_last_error()
+    assert L.dlm_graph_create(2, rp.ctypes.data_as(P), ci.ctypes.data_as(P), None, 0x6, None, C.byref(h)) == -1
+    assert h.value is None
+
+
 def test_null_arguments(L):
     from paper_2109_05948_amd import _abi
     prm = _abi.TabuParams(18, 10, 6, 10, 10, 0, 1, 0, 0, 0, 0)
-    assert L.dlm_tabu_batch(None, C.byref(prm), 1, None, None, None, None, None, None, None) == -1
+    assert L.dlm_tabu_batch(None, C.byref(prm), 1, None, None, None, None, None, None, None, 0, None) == -1
+    sz = C.c_size_t(7)
+    assert L.dlm_tabu_workspace_bytes(None, C.byref(prm), 1, C.byref(sz)) == -1
+    assert sz.value == 0  # cleared on failure
+    assert L.dlm_tabu_workspace_bytes(None, C.byref(prm), 1, None) == -1
     assert L.dlm_graph_info(None, None, None, None) == -1
     assert L.dlm_evaluate(None, 2, None, 1, None, None, None) == -1
     assert L.dlm_init_population(None, 2, 1, 0, 0, 0, None, None, None) == -1

@@ -26,7 +26,7 @@ def say(*a):
 @pytest.fixture(scope="module")
 def dlm():
     import paper_2109_05948_amd as dlm
-    assert dlm.abi_version() == 1
+    assert dlm.abi_version() == 2
     return dlm
 
 
@@ -310,3 +310,46 @@ def test_tenure_slopes(dlm, dev, num, den):
     say(f"tabu tenure {num}/{den}")
     gpu = gpu_run(dlm, g, starts, k, T, 12, ten_num=num, ten_den=den, table="split8")
     compare(gpu, ref, range(pop), f"tenure {num}/{den}")
+
+
+def test_workspace_contract(dlm, dev):
+    """The size query matches the call: an exact workspace runs (twice, the
+    second time on a dirty buffer), a smaller or misaligned one is refused
+    before any launch, and the LDS tiers need none."""
+    import ctypes as C
+    from paper_2109_05948_amd import _abi
+    g = gnp(150, 0.5, seed=3)
+    k, T, pop = 16, 3000, 9
+    G = dlm.Graph.from_csr(g)
+    starts = oracle.init_random(g.n, k, pop, seed=2)
+    ref = oracle.tabucol_batch(g, starts, np.arange(pop), k, T, seed=5)
+    kp = (k + 3) // 4 * 4
+    for table, per_ind in [("split8", 2), ("split16", 2), ("global16", 4)]:
+        need = dlm.tabu_workspace_bytes(G, pop, k, T, table=table, block=128)
+        assert need >= pop * (g.n + 1) * kp * per_ind, table
+        big = torch.full((need + 256,), 0xA5, dtype=torch.uint8, device="cuda")
+        ws = big[:need]
+        for rep in range(2):
+            say(f"tabu workspace table={table} bytes={need} rep={rep}")
+            col = torch.from_numpy(starts.copy()).cuda()
+            r = dlm.tabu_batch(G, col, k, T, 5, table=table, block=128, workspace=ws)
+            torch.cuda.synchronize()
+            gpu = {kk: (v.cpu().numpy() if isinstance(v, torch.Tensor) else v) for kk, v in r.items()}
+            gpu["hash"] = gpu["hash"].view(np.uint64)
+            compare(gpu, ref, range(pop), f"{table} workspace rep {rep}")
+        col = torch.from_numpy(starts.copy()).cuda()
+        with pytest.raises(dlm.DlmError) as e:
+            dlm.tabu_batch(G, col, k, T, 5, table=table, block=128, workspace=ws[: need - 1])
+        assert e.value.code == -1 and "workspace" in str(e.value)
+        with pytest.raises(dlm.DlmError) as e:  # 256-byte alignment
+            dlm.tabu_batch(G, col, k, T, 5, table=table, block=128, workspace=big[16:16 + need])
+        assert e.value.code == -1
+        # a NULL workspace with a nonzero need is refused too
+        prm = _abi._tabu_params(k, T, 5, 0, 6, 10, 10, 128, table, 0)
+        f = torch.empty(pop, dtype=torch.int32, device="cuda")
+        rc = _abi.lib().dlm_tabu_batch(G.handle, C.byref(prm), pop, _abi._ptr(col), _abi._ptr(f), _abi._ptr(f),
+                                       None, None, None, None, 0, None)
+        assert rc == -1
+    assert dlm.tabu_workspace_bytes(G, pop, k, T, table="lds16") == 0
+    assert dlm.tabu_workspace_bytes(G, pop, k, T, table="lds32") == 0
+    assert dlm.tabu_workspace_bytes(G, 0, k, T, table="split8") == 0
