@@ -9,14 +9,16 @@ uploaded once, before timing.  Step s uses initial-colouring seed
 1 + s so every step searches new individuals.
 
 Prints ONE JSON line (rank 0).  value = total tabu moves / timed wall time.
-roofline: the TabuCol kernel is bound by vector instruction issue and the
-latency of its per-move chain, not by memory, so the primary roofline is
-"alu": algorithmic integer operations (a fixed per-candidate and
-per-neighbour model over the recorded counters) / the kernel's average
-duration measured with HIP events on the launch stream, against 256 CU x
-64 lanes x 2.4 GHz.  roofline_lds and roofline_hbm give the algorithmic LDS
-and device-memory bytes against their peaks; traffic is the HBM byte count
-measured with rocprofv3 for the same launch.
+roofline (primary): the LDS-bandwidth bound of the TabuCol kernel with a
+fixed byte model per iteration and move (entry sizes 2 B for gamma, tabu
+expiry and colour, 4 B gamma on the 18-colour G(100, 0.5) workload), summed
+over the kernel's exact counters (conflicting vertices scanned, degrees of
+the moved vertices, moves), divided by the kernel's average duration from
+HIP events on the launch stream, against the nominal 256 CU x 128 B/clk x
+2.4 GHz and against the peak a probe kernel measures in the same run.
+roofline_alu, roofline_lds_tier (the table tier's own entry sizes) and
+roofline_hbm are secondary views of the same launch; traffic is the HBM byte
+count measured with rocprofv3 for the same launch.
 cpu_baseline: the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -81,9 +83,9 @@ TIER_BYTES = {"lds16": (2, 2, 0, 0), "lds32": (4, 4, 0, 0), "split16": (2, 0, 0,
 
 
 def lds_bytes(st: np.ndarray, k: int, table: str = "lds16", s_col: int = 2) -> float:
-    """Algorithmic LDS bytes of a TabuCol run from its counters.
+    """Algorithmic LDS bytes of a TabuCol run from its counters, with the
+    entry sizes of the table tier (g, u: LDS bytes of a gamma and a tabu entry).
 
-    With g, u the LDS bytes of a gamma and a tabu entry of the table tier:
     per iteration: C_t (k-1) (g + u)     [candidate scan]
                  + C_t (g + s_col)       [current colour and its gamma]
     per move:      deg(v*) (4 g + s_col) [neighbour gamma updates, read + write]
@@ -91,8 +93,20 @@ def lds_bytes(st: np.ndarray, k: int, table: str = "lds16", s_col: int = 2) -> f
     st columns: 0 moves, 2 sum C_t, 3 sum deg(v*).
     """
     g, u = TIER_BYTES[table][:2]
-    moves, sum_c, sum_deg = st[:, 0].sum(), st[:, 2].sum(), st[:, 3].sum()
-    return float(sum_c * ((k - 1) * (g + u) + g + s_col) + sum_deg * (4 * g + s_col) + moves * (u + s_col))
+    return lds_model_bytes(st, k, g, u, s_col)
+
+
+def lds_model_bytes(st: np.ndarray, k: int, s_g: int, s_t: int, s_col: int) -> float:
+    """The same byte model with given entry sizes."""
+    moves, sum_c, sum_deg = float(st[:, 0].sum()), float(st[:, 2].sum()), float(st[:, 3].sum())
+    return sum_c * ((k - 1) * (s_g + s_t) + s_g + s_col) + sum_deg * (4 * s_g + s_col) + moves * (s_t + s_col)
+
+
+def fixed_lds_bytes(st: np.ndarray, k: int) -> float:
+    """The fixed model that does not depend on the storage chosen: gamma,
+    tabu and colour entries of 2 bytes each (4-byte gamma when k <= 18, the
+    G(100, 0.5) workload's int32 table)."""
+    return lds_model_bytes(st, k, 4 if k <= 18 else 2, 2, 2)
 
 
 def alu_ops(st: np.ndarray, k: int) -> float:
@@ -115,6 +129,15 @@ def hbm_bytes(st: np.ndarray, k: int, table: str = "lds16") -> float:
     g, u = TIER_BYTES[table][2:]
     moves, sum_c, sum_deg = st[:, 0].sum(), st[:, 2].sum(), st[:, 3].sum()
     return float(4 * sum_deg + sum_c * ((k - 1) * (g + u) + g) + sum_deg * 4 * g + moves * u)
+
+
+def host_cores() -> int:
+    """Cores this process may run on (the affinity mask, which is what the
+    oracle's OpenMP threads can use)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(g, k, T, seed, init_seed, count, threads):
@@ -246,12 +269,20 @@ def main():
         f"moves {moves}; no-ops {int(st[:, 1].sum())}")
 
     traffic = measured_traffic(args.table, args.block) if pop == w.pop else None
-    per_launch_lds = lds_bytes(st, k, args.table) / args.steps
+    sec = kern_ms * 1e-3
+    per_launch = {"moves": float(st[:, 0].sum()) / args.steps, "sum_conflicting": float(st[:, 2].sum()) / args.steps,
+                  "sum_deg": float(st[:, 3].sum()) / args.steps, "noops": float(st[:, 1].sum()) / args.steps}
+    fixed_lds = fixed_lds_bytes(st, k) / args.steps
+    tier_lds = lds_bytes(st, k, args.table) / args.steps
     per_launch_ops = alu_ops(st, k) / args.steps
-    alu_tops = per_launch_ops / (kern_ms * 1e-3) / 1e12
-    per_launch_hbm = hbm_bytes(st, k, args.table) / args.steps
-    lds_gbs = per_launch_lds / (kern_ms * 1e-3) / 1e9
-    hbm_gbs = per_launch_hbm / (kern_ms * 1e-3) / 1e9
+    # HBM per the fixed model: the CSR row of every moved vertex
+    fixed_hbm = 4.0 * per_launch["sum_deg"]
+    tier_hbm = hbm_bytes(st, k, args.table) / args.steps
+    lds_gbs, hbm_gbs = fixed_lds / sec / 1e9, fixed_hbm / sec / 1e9
+    alu_tops = per_launch_ops / sec / 1e12
+    # the LDS peak measured by the probe kernel on this device, in this run
+    probe_gbs = dlm.probe_lds_bandwidth(20000) / 1e9
+    log(f"LDS probe {probe_gbs:.0f} GB/s")
     out = {
         "metric": METRIC,
         "value": moves / dt,
@@ -268,18 +299,45 @@ def main():
         "config": {"workload": args.workload, "graph": f"G(n={g.n}, p=0.5) seed 0", "k": k,
                    "population": pop, "iters_per_individual": T, "block": args.block,
                    "table": args.table, "parallelism": "population (one workgroup per individual)"},
-        "roofline": {"bound": "alu", "achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": alu_tops / ALU_PEAK_TOPS, "traffic": traffic,
-                     "kernel": "tabucol_kernel", "kernel_ms": kern_ms, "ops_per_launch": per_launch_ops},
-        "roofline_lds": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                         "frac": lds_gbs / LDS_PEAK_GBS, "bytes_per_launch": per_launch_lds},
+        "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": traffic,
+                     "peak_measured": probe_gbs, "frac_measured": lds_gbs / probe_gbs,
+                     "model": "fixed entry sizes (gamma, tabu, colour) = (%d, 2, 2) B" % (4 if k <= 18 else 2),
+                     "kernel": "tabucol_kernel", "kernel_ms": kern_ms, "bytes_per_launch": fixed_lds,
+                     "counters_per_launch": per_launch},
         "roofline_hbm": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": hbm_gbs / HBM_PEAK_GBS, "traffic": traffic},
-        "tabu_kernel_moves_per_s": moves / args.steps / (kern_ms * 1e-3),
+                         "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": fixed_hbm, "traffic": traffic,
+                         "model": "CSR row of the moved vertex, 4 B per neighbour"},
+        "roofline_alu": {"bound": "alu", "achieved": alu_tops, "peak": ALU_PEAK_TOPS, "unit": "Tops/s",
+                         "frac": alu_tops / ALU_PEAK_TOPS, "ops_per_launch": per_launch_ops},
+        "roofline_lds_tier": {"bound": "lds", "achieved": tier_lds / sec / 1e9, "peak": LDS_PEAK_GBS,
+                              "unit": "GB/s", "frac": tier_lds / sec / 1e9 / LDS_PEAK_GBS,
+                              "bytes_per_launch": tier_lds, "device_bytes_per_launch": tier_hbm,
+                              "model": f"entry sizes of the {args.table} table"},
+        "tabu_kernel_moves_per_s": moves / args.steps / sec,
     }
+    if args.workload == "gnp500" and pop == w.pop and args.table != "lds16":
+        # the same search with the 16-bit LDS table the configuration names
+        # (gamma and expiry packed in one LDS word): a sample of the population
+        # large enough to fill every CU several times over
+        ns = 4096
+        cs = torch.empty((ns, g.n), dtype=torch.int16, device=dev)
+        dlm.init_population(G, k, ns, seed=w.init_seed, colors=cs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r16 = dlm.tabu_batch(G, cs, k, T, w.tabu_seed, block=256, table="lds16")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s16 = r16["stats"].cpu().numpy()
+        ms16 = e0.elapsed_time(e1)
+        out["lds16_sample"] = {"individuals": ns, "kernel_ms": ms16, "block": 256,
+                               "moves_per_s": float(s16[:, 0].sum()) / (ms16 * 1e-3),
+                               "lds_frac": fixed_lds_bytes(s16, k) / (ms16 * 1e-3) / 1e9 / LDS_PEAK_GBS}
+        log(f"lds16 sample: {ns} individuals in {ms16:.1f} ms")
     if not args.no_cpu_baseline and args.workload == "gnp500":
-        threads = min(os.cpu_count() or 1, 16)
-        log(f"cpu baseline: oracle on {args.cpu_sample} individuals, {threads} threads")
+        threads = host_cores()
+        log(f"cpu baseline: oracle on {args.cpu_sample} individuals, {threads} threads "
+            f"(affinity mask; os.cpu_count() = {os.cpu_count()})")
         out["cpu_baseline"] = cpu_baseline(g, k, T, w.tabu_seed, w.init_seed, args.cpu_sample,
                                            threads)
     print(json.dumps(out), flush=True)

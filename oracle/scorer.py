@@ -19,6 +19,12 @@ LReLU(x) = max(0.2 x, x) (Section 2.3).  Training minimises the mean
 squared error with Adam (Kingma and Ba; beta1 0.9, beta2 0.999, eps 1e-8)
 at learning rate 1e-3 (Section 2.3), one pass of consecutive mini-batches
 per epoch.
+
+The optional operand hook q (identity by default) is applied to both
+operands of the layer-2 products (forward h1 W2; backward da2 W2^T and
+h1^T da2) and to the da2 values summed into the b2 gradient.  It does not
+change the arithmetic when absent; tests pass a rounding or jitter function
+to measure how far low-precision operands move a result.
 """
 from __future__ import annotations
 
@@ -47,11 +53,16 @@ def one_hot(colors: np.ndarray, k: int) -> np.ndarray:
     return X
 
 
-def forward(P: dict, colors: np.ndarray, k: int, keep: bool = False):
+def _identity(a):
+    return a
+
+
+def forward(P: dict, colors: np.ndarray, k: int, keep: bool = False, q=None):
+    q = q or _identity
     X = one_hot(colors, k)
     a1 = X @ P["W1"] + P["b1"]
     h1 = lrelu(a1)
-    a2 = h1 @ P["W2"] + P["b2"]
+    a2 = q(h1) @ q(P["W2"]) + P["b2"]
     h2 = lrelu(a2)
     z = h2.sum(axis=1)
     a3 = z @ P["W3"] + P["b3"]
@@ -62,8 +73,9 @@ def forward(P: dict, colors: np.ndarray, k: int, keep: bool = False):
     return y
 
 
-def backward(P: dict, cache: dict, dy: np.ndarray) -> dict:
+def backward(P: dict, cache: dict, dy: np.ndarray, q=None) -> dict:
     """Gradients of sum_b dy[b] * y[b] with respect to every parameter."""
+    q = q or _identity
     g = {}
     g["b4"] = np.array([dy.sum()])
     g["w4"] = cache["h3"].T @ dy
@@ -72,9 +84,9 @@ def backward(P: dict, cache: dict, dy: np.ndarray) -> dict:
     g["b3"] = da3.sum(axis=0)
     dz = da3 @ P["W3"].T
     da2 = dz[:, None, :] * lrelu_grad(cache["a2"])
-    g["W2"] = np.einsum("bkh,bko->ho", cache["h1"], da2)
-    g["b2"] = da2.sum(axis=(0, 1))
-    dh1 = da2 @ P["W2"].T
+    g["W2"] = np.einsum("bkh,bko->ho", q(cache["h1"]), q(da2))
+    g["b2"] = q(da2).sum(axis=(0, 1))
+    dh1 = q(da2) @ q(P["W2"]).T
     da1 = dh1 * lrelu_grad(cache["a1"])
     g["W1"] = np.einsum("bkn,bkh->nh", cache["X"], da1)
     g["b1"] = da1.sum(axis=(0, 1))
@@ -107,7 +119,7 @@ class Adam:
 
 
 def train(P: dict, colors: np.ndarray, targets: np.ndarray, k: int, batch: int, epochs: int,
-          lr: float = 1e-3, opt: Adam | None = None):
+          lr: float = 1e-3, opt: Adam | None = None, q=None):
     """Epochs of consecutive mini-batches; returns (params, optimiser, losses)."""
     P = {kk: np.array(v, dtype=np.float64) for kk, v in P.items()}
     opt = opt or Adam(P, lr=lr)
@@ -115,9 +127,9 @@ def train(P: dict, colors: np.ndarray, targets: np.ndarray, k: int, batch: int, 
     N = colors.shape[0]
     for _ in range(epochs):
         for s in range(0, N, batch):
-            y, cache = forward(P, colors[s:s + batch], k, keep=True)
+            y, cache = forward(P, colors[s:s + batch], k, keep=True, q=q)
             loss, dy = mse(y, targets[s:s + batch])
-            G = backward(P, cache, dy)
+            G = backward(P, cache, dy, q=q)
             opt.step(P, G)
             losses.append(loss)
     return P, opt, losses

@@ -239,3 +239,69 @@ def test_weighted_memetic_loop_invariant_network(dlm, dev):
     legal = (res.f != 0x7fffffff)
     assert legal.any() and (conf[legal] == 0).all()
     assert (ws[legal] == res.f[legal]).all()
+
+
+def _weighted_replay_start(g, pop, iters, rounds, seed):
+    """The oracle's side of the WVCP loop's start: greedy colourings
+    (Section 2.1), k = the most colours any uses, then Algorithm 2."""
+    from paper_2109_05948_amd import memetic
+    starts, used = zip(*(oracle.greedy_init(g, seed=seed, ind=i) for i in range(pop)))
+    k = max(used)
+    r0 = oracle.wvcp_batch(g, np.stack(starts), np.arange(pop), k, iters, rounds, seed ^ memetic.SEED_TABU)
+    return k, r0["colors"], r0["best_legal"]
+
+
+def test_weighted_generation_replay(dlm, dev):
+    """One generation of the WVCP loop (simplified form, plain selection)
+    replayed step by step with the oracle: greedy start, Algorithm 2 on the
+    population, random pairing, GPX (4 children per pair), random 25 %,
+    Algorithm 2 on the kept offspring, (mu + lambda) update by best legal
+    weighted score.  The resulting population and scores must be identical."""
+    from paper_2109_05948_amd import memetic
+    from workloads.graphs import uniform_weights
+    g = gnp(70, 0.3, seed=6).with_weights(uniform_weights(70, 1, 100, seed=8))
+    pop, iters, rounds, seed = 16, 300, 3, 5
+    G = dlm.Graph.from_csr(g)
+    say("weighted generation replay")
+    res = memetic.run(G, 0, pop, iters, learned=False, seed=seed, cutoff_s=60, max_generations=1,
+                      weighted=True, rounds=rounds)
+    assert res.generations == 1
+    k, cols, f = _weighted_replay_start(g, pop, iters, rounds, seed)
+    nchild = 4 * pop
+    pairs = oracle.random_pairs(pop, seed ^ memetic.SEED_PAIR, 1)
+    children = oracle.gpx_batch(k, cols, pairs, 4, nchild, seed ^ memetic.SEED_GPX)
+    idx = oracle.select(np.zeros(nchild, np.float32), pop, 1, seed=seed ^ memetic.SEED_SEL, gen=1)
+    r1 = oracle.wvcp_batch(g, children[idx], np.arange(pop, 2 * pop), k, iters, rounds, seed ^ memetic.SEED_TABU)
+    rows = np.concatenate([cols, r1["colors"]])
+    fs = np.concatenate([f, r1["best_legal"]])
+    order = np.argsort(fs, kind="stable")[:pop]
+    assert (fs < 0x7FFFFFFF).any()
+    assert (res.f.cpu().numpy() == fs[order]).all()
+    assert (res.colors.cpu().numpy() == rows[order]).all()
+
+
+def test_weighted_diversity_generation_replay(dlm, dev):
+    """The same with the paper's diversity steps (Sections 2.4 to 2.6):
+    nearest neighbours by partition distance, one GPX child per pair, one
+    random child per group, spacing update of the pool."""
+    from oracle import diversity as dv
+    from paper_2109_05948_amd import memetic
+    from workloads.graphs import uniform_weights
+    g = gnp(80, 0.3, seed=7).with_weights(uniform_weights(80, 1, 100, seed=9))
+    pop, iters, rounds, seed, K = 20, 300, 3, 4, 5
+    G = dlm.Graph.from_csr(g)
+    say("weighted diversity generation replay")
+    res = memetic.run(G, 0, pop, iters, learned=False, seed=seed, cutoff_s=60, max_generations=1,
+                      weighted=True, rounds=rounds, diversity=True, neighbours=K)
+    assert res.generations == 1
+    k, cols, f = _weighted_replay_start(g, pop, iters, rounds, seed)
+    nn = dv.nearest(dv.distance_matrix(cols, cols, k), K)
+    pairs = np.stack([np.repeat(np.arange(pop), K), nn.reshape(-1)], 1).astype(np.int32)
+    children = oracle.gpx_batch(k, cols, pairs, 1, pop * K, seed ^ memetic.SEED_GPX)
+    off = children[dv.select_groups(None, pop, K, "random", seed=seed ^ memetic.SEED_SEL, gen=1)]
+    r1 = oracle.wvcp_batch(g, off, np.arange(pop, 2 * pop), k, iters, rounds, seed ^ memetic.SEED_TABU)
+    rows = np.concatenate([cols, r1["colors"]])
+    fs = np.concatenate([f, r1["best_legal"]])
+    pick, _ = dv.spacing_update(fs, dv.distance_matrix(rows, rows, k), pop, g.n // 10)
+    assert (res.f.cpu().numpy() == fs[pick]).all()
+    assert (res.colors.cpu().numpy() == rows[pick]).all()

@@ -79,3 +79,44 @@ def test_autotune_picks_a_valid_config(dlm, dev):
     assert (rates > 0).any() and np.isfinite(rates).all()
     for j, b in zip(jobs, before):   # the items' own colourings are untouched
         assert (j["colors"] == b).all()
+
+
+def test_uneven64_full_plan_sampled(dlm, dev):
+    """The uneven batch at its full size (64 graphs, n in [100, 1000], 256
+    individuals each = 16,384 items, 128 n iterations) as the benchmark runs
+    it: autotuned, one persistent launch.  Four individuals of every graph
+    (0, 85, 170, 255) are replayed by the oracle; the rest must be legal
+    results (f_best equal to a recount of the returned colouring)."""
+    from workloads import workload
+    w = workload("uneven64")
+    jobs, starts = [], []
+    for gi, (g, k, T) in enumerate(zip(w.graphs, w.k, w.iters)):
+        G = dlm.Graph.from_csr(g)
+        st = oracle.init_random(g.n, k, w.pop, seed=w.init_seed, ind_base=gi * w.pop)
+        starts.append(st)
+        jobs.append({"graph": G, "g": g, "colors": torch.from_numpy(st).cuda(), "k": k, "iters": T,
+                     "seed": w.tabu_seed, "ind_base": gi * w.pop})
+    say("uneven64: autotune")
+    (block, budget), _ = dlm.MultiBatch.autotune(jobs, calib_iters=1000)
+    say(f"uneven64: plan block={block} budget={budget}, one launch of {64 * w.pop} items")
+    mb = dlm.MultiBatch(jobs, block=block, lds_budget=budget)
+    assert mb.info()["items"] == 64 * w.pop
+    mb.launch()
+    torch.cuda.synchronize()
+    idx = np.array([0, 85, 170, 255])
+    for gi, (j, st) in enumerate(zip(jobs, starts)):
+        ref = oracle.tabucol_batch(j["g"], st[idx], j["ind_base"] + idx, j["k"], j["iters"], seed=j["seed"])
+        fb = j["f_best"].cpu().numpy()
+        it = j["iters_out"].cpu().numpy()
+        hs = j["hash"].cpu().numpy().view(np.uint64)
+        col = j["colors"].cpu().numpy()
+        stats = j["stats"].cpu().numpy()
+        for r, i in enumerate(idx):
+            msg = f"graph {gi} (n={j['g'].n}, k={j['k']}) individual {i}"
+            assert fb[i] == ref["f_best"][r], msg
+            assert it[i] == ref["iters"][r], msg
+            assert hs[i] == ref["hash"][r], msg
+            assert (col[i] == ref["colors"][r]).all(), msg
+            assert (stats[i][:6] == ref["stats"][r][:6]).all(), msg
+        conf, _ = dlm.evaluate(j["graph"], j["colors"], j["k"])
+        assert (conf.cpu().numpy() == fb).all(), f"graph {gi}: f_best differs from the recount"

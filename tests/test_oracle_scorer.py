@@ -122,3 +122,29 @@ def test_init_shapes(n):
     total = sum(v.size for v in W.values())
     assert total == n * 256 + 256 + 256 * 128 + 128 + 128 * 64 + 64 + 64 + 1
     assert all(v.dtype == np.float32 for v in W.values())
+
+
+def test_operand_hook_reaches_the_layer2_products():
+    """The operand hook (used to measure the GPU parity tolerance) scales
+    both operands of each layer-2 product: with q = multiplication by c, the
+    layer-2 pre-activation moves to b2 + c^2 (a2 - b2); given the same
+    cached activations, the W2, h1 and so W1 / b1 gradients scale by c^2,
+    the b2 gradient by c, and the head's gradients do not change."""
+    n, k, B, c = 12, 4, 3, 1.5
+    P = _params(n, seed=2)
+    rng = np.random.default_rng(6)
+    cols = rng.integers(0, k, (B, n))
+    q = lambda a: c * np.asarray(a)  # noqa: E731
+    _, c0 = scorer.forward(P, cols, k, keep=True)
+    _, c1 = scorer.forward(P, cols, k, keep=True, q=q)
+    assert np.allclose(c1["a2"] - P["b2"], c * c * (c0["a2"] - P["b2"]), rtol=1e-12, atol=1e-14)
+    assert np.allclose(c1["a1"], c0["a1"])  # layer 1 is a gather, not hooked
+    dy = rng.normal(size=B)
+    g = scorer.backward(P, c0, dy)
+    gq = scorer.backward(P, c0, dy, q=q)
+    for nm in ("W2", "W1", "b1"):
+        assert np.allclose(gq[nm], c * c * g[nm], rtol=1e-12, atol=1e-14), nm
+    assert np.allclose(gq["b2"], c * g["b2"], rtol=1e-12)
+    for nm in ("W3", "b3", "w4", "b4"):
+        assert np.array_equal(gq[nm], g[nm]), nm
+    assert np.abs(g["W2"]).max() > 1e-6 and np.abs(g["W1"]).max() > 1e-6
