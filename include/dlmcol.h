@@ -185,6 +185,30 @@ int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
                    int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev,
                    void* workspace_dev, size_t workspace_bytes, void* stream);
 
+/*
+ * dlm_tabu_batch for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, hosts that forbid hipMalloc): the
+ * same search with the same arguments and bit-identical outputs, but its
+ * workspace is a fixed array of DLM_STATIC_SCRATCH_BYTES in the library's
+ * device code (one per GPU, held from the library's load until the process
+ * ends) instead of a caller-owned buffer.  The call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  The array's device
+ * address is looked up once per device, on the first call made with that
+ * device current.
+ *   Every call on one GPU shares that GPU's array: calls that overlap on one
+ *   GPU (two streams, two host threads) race and give undefined results;
+ *   calls ordered on one stream, or separated by synchronisation, are safe.
+ *   Nothing in the array needs clearing between calls: each launch writes
+ *   every byte of the workspace it reads first.
+ * Errors: as dlm_tabu_batch; DLM_E_UNSUPPORTED when the workspace this call
+ * would need (dlm_tabu_workspace_bytes) exceeds DLM_STATIC_SCRATCH_BYTES, in
+ * which case nothing is launched.
+ */
+#define DLM_STATIC_SCRATCH_BYTES (64ull << 20)
+int dlm_tabu_batch_static(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                          int16_t* colors_dev, int32_t* f_best_dev, int32_t* iters_dev,
+                          int64_t* stats_dev, uint64_t* hash_dev, int32_t* trace_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * Uneven batches: the populations of many graphs (any mix of n, k and
  * iteration budgets) searched by one persistent launch.  Each item is a

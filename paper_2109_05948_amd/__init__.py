@@ -31,6 +31,7 @@ from ._abi import (  # noqa: F401
     invnet_names,
     lib,
     tabu_batch,
+    tabu_batch_static,
     tabu_workspace_bytes,
     wvcp_batch,
 )

@@ -27,7 +27,8 @@ INIT_MODES = {"random": 0, "greedy": 1}
 
 EXPORTS = [
     "dlm_abi_version", "dlm_last_error", "dlm_graph_create", "dlm_graph_destroy", "dlm_graph_info",
-    "dlm_init_population", "dlm_tabu_workspace_bytes", "dlm_tabu_batch", "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
+    "dlm_init_population", "dlm_tabu_workspace_bytes", "dlm_tabu_batch", "dlm_tabu_batch_static",
+    "dlm_evaluate", "dlm_gpx_batch", "dlm_select",
     "dlm_wvcp_batch", "dlm_scorer_create", "dlm_scorer_destroy", "dlm_scorer_num_params",
     "dlm_scorer_get_params", "dlm_score_offspring", "dlm_scorer_grad", "dlm_scorer_train",
     "dlm_gather_rows", "dlm_standardize", "dlm_random_pairs", "dlm_pop_update",
@@ -71,6 +72,7 @@ def lib():
             L.dlm_init_population.argtypes = [P, I32, I32, U64, I32, I32, P, P, P]
             L.dlm_tabu_workspace_bytes.argtypes = [P, C.POINTER(TabuParams), I32, C.POINTER(C.c_size_t)]
             L.dlm_tabu_batch.argtypes = [P, C.POINTER(TabuParams), I32, P, P, P, P, P, P, P, C.c_size_t, P]
+            L.dlm_tabu_batch_static.argtypes = [P, C.POINTER(TabuParams), I32, P, P, P, P, P, P, P]
             L.dlm_evaluate.argtypes = [P, I32, P, I32, P, P, P]
             L.dlm_gpx_batch.argtypes = [P, I32, P, I32, P, I32, I32, U64, C.c_uint32, P, P]
             L.dlm_select.argtypes = [P, I32, I32, I32, U64, C.c_uint32, P, P, P]
@@ -255,6 +257,28 @@ def tabu_batch(graph: Graph, colors: torch.Tensor, k: int, max_iters: int, seed:
                                 _ptr(o.get("trace")), _ptr(workspace), ws_bytes, _stream(stream)))
     o["colors"] = colors
     return o
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # DLM_STATIC_SCRATCH_BYTES
+
+
+def tabu_batch_static(graph: Graph, colors: torch.Tensor, k: int, max_iters: int, seed: int, out: dict,
+                      ind_base: int = 0, ten_num: int = 6, ten_den: int = 10, ten_rand: int = 10,
+                      block: int = 0, table: str = "auto", trace_cap: int = 0, stream=None) -> dict:
+    """dlm_tabu_batch_static: dlm_tabu_batch with the library's fixed device
+    scratch as its workspace.  Nothing is allocated here either: ``out``
+    holds the caller's f_best, iters and (or None) stats, hash, trace tensors."""
+    _dev(colors, torch.int16, "colors")
+    pop = colors.shape[0]
+    if colors.dim() != 2 or colors.shape[1] != graph.n:
+        raise ValueError(f"colors must be [pop, {graph.n}]")
+    prm = _tabu_params(k, max_iters, seed, ind_base, ten_num, ten_den, ten_rand, block, table, trace_cap)
+    _check("dlm_tabu_batch_static",
+           lib().dlm_tabu_batch_static(graph.handle, C.byref(prm), pop, _ptr(colors), _ptr(out["f_best"]),
+                                       _ptr(out["iters"]), _ptr(out.get("stats")), _ptr(out.get("hash")),
+                                       _ptr(out.get("trace")), _stream(stream)))
+    out["colors"] = colors
+    return out
 
 
 def evaluate(graph: Graph, colors: torch.Tensor, k: int, weighted: bool = False, stream=None):

@@ -28,6 +28,8 @@
 // The byte-gamma tier gives up on an individual whose colour classes would
 // pass 255 vertices; a rerun kernel repeats those from their start colouring
 // with the 16-bit device table, so every tier returns the same result.
+#include <mutex>
+
 #include "tabu_body.h"
 
 namespace dlm {
@@ -159,11 +161,11 @@ static int tabu_check(const char* fn, const dlm_graph* g, const dlm_tabu_params*
 }
 
 static int tabu_plan(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop, TabuPlan& P) {
+  const int n = g->n, k = p->k;
+  const int64_t lds_max = device_lds_limit();
   int block = p->block ? p->block : 256;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return set_error(DLM_E_INVAL, "%s: block=%d not in {64,128,256,512,1024}", fn, block);
-  const int n = g->n, k = p->k;
-  const int64_t lds_max = device_lds_limit();
   int table = p->table;
   if (table == DLM_TABLE_AUTO) {
     // the LDS tier that keeps more individuals resident per CU; byte gamma on a tie loses
@@ -206,6 +208,78 @@ static int tabu_plan(const char* fn, const dlm_graph* g, const dlm_tabu_params* 
   return DLM_OK;
 }
 
+// The search itself, after the caller's arguments passed tabu_check: plan,
+// workspace checks, launches.  Shared by both entry points.
+static int tabu_run(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                    int16_t* colors, int32_t* f_best, int32_t* iters, int64_t* stats, uint64_t* hash,
+                    int32_t* trace, void* workspace, size_t workspace_bytes, hipStream_t s,
+                    uint64_t ws_limit) {
+  if (p->trace_cap > 0 && !trace)
+    return set_error(DLM_E_INVAL, "%s: trace_cap=%d needs a trace buffer", fn, p->trace_cap);
+  if (pop == 0) return DLM_OK;
+  if (!colors || !f_best || !iters) return set_error(DLM_E_INVAL, "%s: null output buffer", fn);
+  TabuPlan P;
+  int rc;
+  if ((rc = tabu_plan(fn, g, p, pop, P)) != DLM_OK) return rc;
+  if (P.ws_bytes > ws_limit)
+    return set_error(DLM_E_UNSUPPORTED, "%s: %llu bytes of workspace needed, the fixed scratch holds %llu", fn,
+                     (unsigned long long)P.ws_bytes, (unsigned long long)ws_limit);
+  if (P.ws_bytes > 0 && (!workspace || workspace_bytes < P.ws_bytes))
+    return set_error(DLM_E_INVAL, "%s: workspace of %zu bytes at %p, %llu needed (dlm_tabu_workspace_bytes)", fn,
+                     workspace_bytes, workspace, (unsigned long long)P.ws_bytes);
+  if (P.ws_bytes > 0 && (reinterpret_cast<uintptr_t>(workspace) & 255u))
+    return set_error(DLM_E_INVAL, "%s: workspace must be 256-byte aligned", fn);
+  const int n = g->n, k = p->k;
+  unsigned char* ws = static_cast<unsigned char*>(workspace);
+  TabuArgs a{g->row_ptr, g->col_idx, g->erow, colors, f_best, iters, stats, hash, trace, nullptr,
+             make_key(p->seed), n, k, p->max_iters, p->ten_num, p->ten_den, p->ten_rand,
+             p->ind_base, p->trace_cap};
+  if (P.gtab_bytes > 0) a.gtab = ws;
+  switch (P.table) {
+    case DLM_TABLE_SPLIT8: {
+      int16_t* start = reinterpret_cast<int16_t*>(ws + align256(P.gtab_bytes));
+      unsigned char* slot_mem = ws + align256(P.gtab_bytes) + align256(P.start_bytes);
+      const int64_t cells = (int64_t)pop * n;
+      hipLaunchKernelGGL(copy_i16_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, colors, start,
+                         cells);
+      DLM_HIP(hipGetLastError());
+      if ((rc = launch_tab<TabSplit8>(a, pop, P.block, P.lds, s)) != DLM_OK) return rc;
+      const Rerun rr{start, slot_mem, (int32_t)P.slots};
+      return launch_tab<TabGlobal16>(a, pop, P.block, P.lds_rr, s, &rr);
+    }
+    case DLM_TABLE_SPLIT16: return launch_tab<TabSplit16>(a, pop, P.block, P.lds, s);
+    case DLM_TABLE_GLOBAL16: return launch_tab<TabGlobal16>(a, pop, P.block, P.lds, s);
+    case DLM_TABLE_LDS32: return launch_tab<TabLds32>(a, pop, P.block, P.lds, s);
+    default: return launch_tab<TabLds16>(a, pop, P.block, P.lds, s);
+  }
+}
+
+// Fixed device scratch of the allocation-free entry point.  In host code the
+// array's name is only a stand-in: its device address, one per GPU, comes
+// from hipGetSymbolAddress on the first call on that device and is the only
+// form host code hands to kernels.  Every call on a device shares the array.
+constexpr uint64_t kStaticScratchBytes = DLM_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static int static_scratch(const char* fn, void** out) {
+  int dev = -1;
+  DLM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(DLM_E_UNSUPPORTED, "%s: device %d >= %d", fn, dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_error(DLM_E_HIP, "%s: hipGetSymbolAddress gave a null scratch address", fn);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DLM_OK;
+}
+
 }  // namespace dlm
 
 using namespace dlm;
@@ -226,41 +300,21 @@ extern "C" int dlm_tabu_batch(const dlm_graph* g, const dlm_tabu_params* p, int3
                               int16_t* colors, int32_t* f_best, int32_t* iters, int64_t* stats,
                               uint64_t* hash, int32_t* trace, void* workspace, size_t workspace_bytes,
                               void* stream) {
-  int rc = tabu_check("dlm_tabu_batch", g, p, pop);
+  const int rc = tabu_check("dlm_tabu_batch", g, p, pop);
   if (rc != DLM_OK) return rc;
-  if (p->trace_cap > 0 && !trace)
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: trace_cap=%d needs a trace buffer", p->trace_cap);
+  return tabu_run("dlm_tabu_batch", g, p, pop, colors, f_best, iters, stats, hash, trace, workspace,
+                  workspace_bytes, (hipStream_t)stream, ~0ull);
+}
+
+extern "C" int dlm_tabu_batch_static(const dlm_graph* g, const dlm_tabu_params* p, int32_t pop,
+                                     int16_t* colors, int32_t* f_best, int32_t* iters, int64_t* stats,
+                                     uint64_t* hash, int32_t* trace, void* stream) {
+  const char* fn = "dlm_tabu_batch_static";
+  int rc = tabu_check(fn, g, p, pop);
+  if (rc != DLM_OK) return rc;
   if (pop == 0) return DLM_OK;
-  if (!colors || !f_best || !iters) return set_error(DLM_E_INVAL, "dlm_tabu_batch: null output buffer");
-  TabuPlan P;
-  if ((rc = tabu_plan("dlm_tabu_batch", g, p, pop, P)) != DLM_OK) return rc;
-  if (P.ws_bytes > 0 && (!workspace || workspace_bytes < P.ws_bytes))
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: workspace of %zu bytes at %p, %llu needed (dlm_tabu_workspace_bytes)",
-                     workspace_bytes, workspace, (unsigned long long)P.ws_bytes);
-  if (P.ws_bytes > 0 && (reinterpret_cast<uintptr_t>(workspace) & 255u))
-    return set_error(DLM_E_INVAL, "dlm_tabu_batch: workspace must be 256-byte aligned");
-  const int n = g->n, k = p->k;
-  unsigned char* ws = static_cast<unsigned char*>(workspace);
-  TabuArgs a{g->row_ptr, g->col_idx, g->erow, colors, f_best, iters, stats, hash, trace, nullptr,
-             make_key(p->seed), n, k, p->max_iters, p->ten_num, p->ten_den, p->ten_rand,
-             p->ind_base, p->trace_cap};
-  hipStream_t s = (hipStream_t)stream;
-  if (P.gtab_bytes > 0) a.gtab = ws;
-  switch (P.table) {
-    case DLM_TABLE_SPLIT8: {
-      int16_t* start = reinterpret_cast<int16_t*>(ws + align256(P.gtab_bytes));
-      unsigned char* slot_mem = ws + align256(P.gtab_bytes) + align256(P.start_bytes);
-      const int64_t cells = (int64_t)pop * n;
-      hipLaunchKernelGGL(copy_i16_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, colors, start,
-                         cells);
-      DLM_HIP(hipGetLastError());
-      if ((rc = launch_tab<TabSplit8>(a, pop, P.block, P.lds, s)) != DLM_OK) return rc;
-      const Rerun rr{start, slot_mem, (int32_t)P.slots};
-      return launch_tab<TabGlobal16>(a, pop, P.block, P.lds_rr, s, &rr);
-    }
-    case DLM_TABLE_SPLIT16: return launch_tab<TabSplit16>(a, pop, P.block, P.lds, s);
-    case DLM_TABLE_GLOBAL16: return launch_tab<TabGlobal16>(a, pop, P.block, P.lds, s);
-    case DLM_TABLE_LDS32: return launch_tab<TabLds32>(a, pop, P.block, P.lds, s);
-    default: return launch_tab<TabLds16>(a, pop, P.block, P.lds, s);
-  }
+  void* ws = nullptr;
+  if ((rc = static_scratch(fn, &ws)) != DLM_OK) return rc;
+  return tabu_run(fn, g, p, pop, colors, f_best, iters, stats, hash, trace, ws, (size_t)kStaticScratchBytes,
+                  (hipStream_t)stream, kStaticScratchBytes);
 }
