@@ -127,6 +127,12 @@ int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, uint64_t see
 #define DLM_TABLE_SPLIT8 5     /* gamma 8 bits in LDS, tabu 16 bits in device memory; an individual
                                   whose colour classes would pass 255 vertices is rerun from its
                                   start with GLOBAL16 (same results) */
+#define DLM_TABLE_WAVE8 6      /* one wavefront (block 64) per individual, all in LDS: a byte per (v,c)
+                                  holding gamma (7 bits) and a flag for "current colour or tabu", and a
+                                  list of the live tabu pairs with their expiries; needs k <= 256 and
+                                  n * kp <= 2^17.  An individual whose colour classes would pass 127
+                                  vertices, or whose live tabu pairs would overflow the list, is rerun
+                                  from its start with GLOBAL16 (same results) */
 
 typedef struct dlm_tabu_params {
   int32_t k;          /* colours, 1 <= k <= 32767 */

@@ -22,7 +22,7 @@ _lib = None
 
 NSTATS = 8
 DLM_OK = 0
-TABLES = {"auto": 0, "lds16": 1, "lds32": 2, "global16": 3, "split16": 4, "split8": 5}
+TABLES = {"auto": 0, "lds16": 1, "lds32": 2, "global16": 3, "split16": 4, "split8": 5, "wave8": 6}
 INIT_MODES = {"random": 0, "greedy": 1}
 
 EXPORTS = [

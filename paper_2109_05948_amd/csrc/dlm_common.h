@@ -148,6 +148,7 @@ int set_error(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 int device_lds_limit();  // max dynamic LDS bytes per workgroup on the current device
 int device_cu_count();
+int device_lds_per_cu();  // LDS bytes of one CU on the current device
 
 #define DLM_HIP(call)                                    \
   do {                                                   \

@@ -37,6 +37,14 @@ int device_lds_limit() {
   return v;
 }
 
+int device_lds_per_cu() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || v <= 0)
+    return 65536;
+  return v;
+}
+
 int device_cu_count() {
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;

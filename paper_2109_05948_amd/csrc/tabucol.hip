@@ -31,6 +31,7 @@
 #include <mutex>
 
 #include "tabu_body.h"
+#include "tabu_wave.h"
 
 namespace dlm {
 
@@ -61,6 +62,33 @@ __global__ __launch_bounds__(BLOCK) void tabucol_rerun_kernel(TabuArgs a, const 
     tabu_individual<BLOCK, TabGlobal16>(a, li, slot, smem);
     __syncthreads();
   }
+}
+
+// WAVE8: one wavefront per individual (tabu_wave.h)
+template <int KQ>
+__global__ __launch_bounds__(64) void tabucol_w8_kernel(TabuArgs a, int32_t acap) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  tabu_w8_individual<KQ>(a, blockIdx.x, acap, smem);
+}
+
+template <int KQ>
+static int launch_w8_kq(const TabuArgs& a, int pop, int acap, size_t lds, hipStream_t s) {
+  auto kern = tabucol_w8_kernel<KQ>;
+  DLM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kern, dim3(pop), dim3(64), lds, s, a, acap);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+static int launch_w8(const TabuArgs& a, int pop, int acap, size_t lds, hipStream_t s) {
+  switch (w8_bucket(a.k)) {
+    case 8: return launch_w8_kq<8>(a, pop, acap, lds, s);
+    case 16: return launch_w8_kq<16>(a, pop, acap, lds, s);
+    case 24: return launch_w8_kq<24>(a, pop, acap, lds, s);
+    case 32: return launch_w8_kq<32>(a, pop, acap, lds, s);
+    case 64: return launch_w8_kq<64>(a, pop, acap, lds, s);
+  }
+  return set_error(DLM_E_UNSUPPORTED, "dlm_tabu_batch: k=%d too large for the wave table", a.k);
 }
 
 __global__ void copy_i16_kernel(const int16_t* __restrict__ src, int16_t* __restrict__ dst, int64_t count) {
@@ -138,6 +166,7 @@ struct TabuPlan {
   uint64_t start_bytes = 0;   // SPLIT8: copy of the start colourings
   uint64_t slot_bytes = 0;    // SPLIT8: one rerun slot (packed 16-bit table)
   int64_t slots = 0;          // SPLIT8: rerun slots
+  int32_t acap = 0;           // WAVE8: tabu pairs each individual's LDS holds
   uint64_t ws_bytes = 0;      // total, each part on a 256-byte boundary
 };
 
@@ -163,6 +192,35 @@ static int tabu_check(const char* fn, const dlm_graph* g, const dlm_tabu_params*
 static int tabu_plan(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop, TabuPlan& P) {
   const int n = g->n, k = p->k;
   const int64_t lds_max = device_lds_limit();
+  if (p->table == DLM_TABLE_WAVE8) {
+    if (p->block != 0 && p->block != 64)
+      return set_error(DLM_E_INVAL, "%s: the wave table runs 64 threads per individual (block=%d)", fn, p->block);
+    const uint64_t kp = (uint64_t)tab_stride(k);
+    if (w8_bucket(k) == 0 || (uint64_t)n * kp > (1ull << 17))
+      return set_error(DLM_E_UNSUPPORTED, "%s: n=%d, k=%d outside the wave table (k <= 256, n*kp <= 2^17)", fn, n, k);
+    const uint64_t base = w8_layout(n, k, 0).bytes;
+    const int64_t lds_cu = device_lds_per_cu();
+    if (base + 4u * kWave > (uint64_t)lds_max)
+      return set_error(DLM_E_UNSUPPORTED, "%s: %llu bytes of LDS needed, %lld available", fn,
+                       (unsigned long long)(base + 4u * kWave), (long long)lds_max);
+    // as many individuals per CU as the table allows; the rest of their
+    // share of the CU's LDS holds tabu pairs
+    const int64_t res = std::max<int64_t>(1, std::min<int64_t>(32, lds_cu / (int64_t)(base + 4u * kWave)));
+    const int64_t budget = std::min<int64_t>(lds_max, lds_cu / res) & ~15ll;
+    P.acap = (int32_t)std::min<int64_t>(16384, ((budget - (int64_t)base) / 4) & ~63ll);
+    P.table = DLM_TABLE_WAVE8;
+    P.block = 64;
+    P.lds = w8_layout(n, k, P.acap).bytes;
+    if (pop > 0) {
+      P.slot_bytes = tab_entries(n, k) * TabGlobal16::kGlobalBytes;
+      int64_t slots = std::min<int64_t>(pop, 2 * (int64_t)device_cu_count());
+      P.slots = std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)((1ull << 30) / std::max<uint64_t>(P.slot_bytes, 1))));
+      P.lds_rr = tabu_layout(n, k, 256 / kWave, TabGlobal16::kLdsBytes).bytes;
+      P.start_bytes = sizeof(int16_t) * (uint64_t)pop * (uint64_t)n;
+    }
+    P.ws_bytes = align256(P.start_bytes) + align256(P.slot_bytes * (uint64_t)P.slots);
+    return DLM_OK;
+  }
   int block = p->block ? p->block : 256;
   if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
     return set_error(DLM_E_INVAL, "%s: block=%d not in {64,128,256,512,1024}", fn, block);
@@ -236,6 +294,17 @@ static int tabu_run(const char* fn, const dlm_graph* g, const dlm_tabu_params* p
              p->ind_base, p->trace_cap};
   if (P.gtab_bytes > 0) a.gtab = ws;
   switch (P.table) {
+    case DLM_TABLE_WAVE8: {
+      int16_t* start = reinterpret_cast<int16_t*>(ws);
+      unsigned char* slot_mem = ws + align256(P.start_bytes);
+      const int64_t cells = (int64_t)pop * n;
+      hipLaunchKernelGGL(copy_i16_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, colors, start,
+                         cells);
+      DLM_HIP(hipGetLastError());
+      if ((rc = launch_w8(a, pop, P.acap, P.lds, s)) != DLM_OK) return rc;
+      const Rerun rr{start, slot_mem, (int32_t)P.slots};
+      return launch_tab<TabGlobal16>(a, pop, 256, P.lds_rr, s, &rr);
+    }
     case DLM_TABLE_SPLIT8: {
       int16_t* start = reinterpret_cast<int16_t*>(ws + align256(P.gtab_bytes));
       unsigned char* slot_mem = ws + align256(P.gtab_bytes) + align256(P.start_bytes);
