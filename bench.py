@@ -47,7 +47,7 @@ METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned
 MEASURED_TRAFFIC = {"sources_sha256": "cf4e5663af7ecbe6c68f5b9f43f23ce5679c2bae93ee9f4692b0252fc633a637",
                     "table": "split8", "block": 256, "bytes": 84982992446}  # profiles/tabucol_split8_gnp500.md
 KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd/csrc/tabucol.hip",
-                  "paper_2109_05948_amd/csrc/dlm_common.h")
+                  "paper_2109_05948_amd/csrc/dlm_common.h", "paper_2109_05948_amd/csrc/tabu_wave.h")
 
 
 # HBM bytes of the two distance launches of one diversity step (old x new
@@ -79,7 +79,11 @@ def log(*a):
 
 # bytes of one table entry by tier: (gamma in LDS, tabu in LDS, gamma in device memory, tabu in device memory)
 TIER_BYTES = {"lds16": (2, 2, 0, 0), "lds32": (4, 4, 0, 0), "split16": (2, 0, 0, 2),
-              "split8": (1, 0, 0, 2), "global16": (0, 0, 2, 2)}
+              "split8": (1, 0, 0, 2), "global16": (0, 0, 2, 2),
+              # byte gamma whose top bit flags tabu pairs: no separate tabu entry
+              "wave8": (1, 0, 0, 0)}
+# the search kernel of each table tier (the dominant kernel of a launch)
+TIER_KERNEL = {"wave8": "tabucol_w8_kernel"}
 
 
 def lds_bytes(st: np.ndarray, k: int, table: str = "lds16", s_col: int = 2) -> float:
@@ -303,7 +307,7 @@ def main():
                      "frac": lds_gbs / LDS_PEAK_GBS, "traffic": traffic,
                      "peak_measured": probe_gbs, "frac_measured": lds_gbs / probe_gbs,
                      "model": "fixed entry sizes (gamma, tabu, colour) = (%d, 2, 2) B" % (4 if k <= 18 else 2),
-                     "kernel": "tabucol_kernel", "kernel_ms": kern_ms, "bytes_per_launch": fixed_lds,
+                     "kernel": TIER_KERNEL.get(args.table, "tabucol_kernel"), "kernel_ms": kern_ms, "bytes_per_launch": fixed_lds,
                      "counters_per_launch": per_launch},
         "roofline_hbm": {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": hbm_gbs / HBM_PEAK_GBS, "bytes_per_launch": fixed_hbm, "traffic": traffic,

@@ -23,6 +23,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed-FP32 instruction selection anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # an atomic issued by one lane stays one instruction (the optimizer would
+    # wrap it in a lane count and a broadcast)
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-command-line-argument",
 ]
 

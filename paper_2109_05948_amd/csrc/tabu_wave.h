@@ -52,7 +52,7 @@ constexpr uint32_t kW8ExpMask = 0x7fffu;  // expiries are kept modulo 2^15
 constexpr uint32_t kW8NoKey = 0xffffffffu;
 
 struct W8Layout {
-  uint32_t tab, cg, list, rowkey, stage, csize, act, bytes;
+  uint32_t tab, cg, list, rowkey, stage, csize, sink, act, bytes;
 };
 
 // LDS of one individual with room for acap tabu pairs.  A row read covers
@@ -74,6 +74,8 @@ __host__ __device__ inline W8Layout w8_layout(int n, int k, int acap) {
   o += 4u * kW8Stage;
   L.csize = o;
   o += align16(2u * kp);
+  L.sink = o;  // lanes with nothing to store or add aim here (no branch around them)
+  o += 16;
   L.act = o;
   o += 4u * (uint32_t)acap;
   L.bytes = o;
@@ -100,6 +102,54 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// a uniform 32-bit value in a scalar register of its own (see own_sgpr)
+__device__ __forceinline__ uint32_t own_u32(uint32_t x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+
+// The twenty Philox4x32-10 round keys (the seed's two words bumped by the
+// Weyl constants), computed once and held in vector registers: in scalar
+// registers, the scarce file here, they would spill, and recomputing them
+// per call costs twenty scalar adds.
+struct W8RoundKeys {
+  uint32_t k[20];
+};
+
+__device__ __forceinline__ uint32_t to_vgpr(uint32_t x) {
+  uint32_t y;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(y) : "s"(x));
+  return y;
+}
+
+__device__ __forceinline__ W8RoundKeys w8_round_keys(Key key) {
+  W8RoundKeys rk;
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    rk.k[2 * r] = to_vgpr(k0);
+    rk.k[2 * r + 1] = to_vgpr(k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return rk;
+}
+
+// Philox4x32-10 word 0 (the same function as philox_w0) from precomputed round keys
+__device__ __forceinline__ uint32_t philox_w0_rk(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                                 const W8RoundKeys& rk) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x0, p1 = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ rk.k[2 * r], y2 = (uint32_t)(p0 >> 32) ^ x3 ^ rk.k[2 * r + 1];
+    x1 = (uint32_t)p1;
+    x3 = (uint32_t)p0;
+    x0 = y0;
+    x2 = y2;
+  }
+  return x0;
 }
 
 __device__ __forceinline__ uint32_t rfl(uint32_t x) {
@@ -133,22 +183,45 @@ __device__ __forceinline__ int w8_build_list(uint16_t* cg, uint16_t* list, int n
   return base;
 }
 
+// Drops the stale entries (vertices no longer conflicting) from the list in
+// place and clears their "listed" bit.  Returns the new length.
+__device__ __forceinline__ int w8_compact_list(uint16_t* cg, uint16_t* list, int len, int lane) {
+  int base = 0;
+  for (int i0 = 0; i0 < len; i0 += kWave) {
+    const int i = i0 + lane;
+    const uint32_t v = i < len ? (uint32_t)list[i] : 0u;
+    const uint32_t x = i < len ? (uint32_t)cg[v] : 0u;
+    const bool keep = ((x >> 8) & 0x7fu) != 0u;
+    if (i < len && !keep) cg[v] = (uint16_t)(x & 0x7fffu);
+    const uint64_t m = __ballot(keep);
+    if (keep) list[base + (int)lane_rank(m)] = (uint16_t)v;  // base <= i0: entries are read before they are overwritten
+    base += __popcll(m);
+  }
+  return base;
+}
+
 // One individual (row li of a.colors) searched by the calling wavefront.
 // KQ: dword bucket of the rows (kp / 4 <= KQ); acap: tabu pairs the LDS holds.
 template <int KQ>
 __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, int acap, unsigned char* smem) {
   constexpr int KQ_LO = KQ == 8 ? 0 : (KQ == 16 ? 8 : (KQ == 24 ? 16 : (KQ == 32 ? 24 : 32)));
-  constexpr int W = KQ <= 8 ? 8 : (KQ <= 16 ? 16 : (KQ <= 32 ? 32 : 64));  // lanes per row, tie pass
-  constexpr int P = kWave / W;                                              // rows per tie pass
   const int lane = threadIdx.x;
-  const uint32_t ind = (uint32_t)(a.ind_base + li);
-  const int n = a.n, k = a.k;
+  // every field the search needs, as a value of its own: the argument block
+  // as a whole (about 30 scalar registers) would otherwise stay live in, and
+  // spill from, scalar registers
+  const uint32_t ind = own_u32((uint32_t)(a.ind_base + li));
+  const int n = (int)own_u32((uint32_t)a.n), k = (int)own_u32((uint32_t)a.k);
   const uint32_t kp = (uint32_t)tab_stride(k), kq = kp >> 2;
   const gptr<const int32_t> col_idx = own_sgpr(a.col_idx);
   const gptr<int32_t> trace = own_sgpr(a.trace);
-  const int trace_cap = a.trace_cap, T = a.T;
-  const Key key = a.key;
-  const uint32_t ten_num = (uint32_t)a.ten_num, ten_den = (uint32_t)a.ten_den, ten_rand = (uint32_t)a.ten_rand;
+  const gptr<int32_t> iters_out = own_sgpr(a.iters + li);
+  const gptr<int32_t> f_best_out = own_sgpr(a.f_best + li);
+  const gptr<int64_t> stats_out = own_sgpr(a.stats ? a.stats + (size_t)li * DLM_NSTATS : nullptr);
+  const gptr<uint64_t> hash_out = own_sgpr(a.hash ? a.hash + li : nullptr);
+  const int trace_cap = (int)own_u32((uint32_t)a.trace_cap), T = (int)own_u32((uint32_t)a.T);
+  const Key key{own_u32(a.key.k0), own_u32(a.key.k1)};
+  const uint32_t ten_num = own_u32((uint32_t)a.ten_num), ten_den = own_u32((uint32_t)a.ten_den);
+  const uint32_t ten_rand = own_u32((uint32_t)a.ten_rand);
   const uint32_t den_inv = 0xffffffffu / ten_den;
   // ceil(2^32 / kp): v = umulhi(v*kp + c, kp_inv) is exact for v*kp + c < 2^17
   const uint32_t kp_inv = (uint32_t)((0x100000000ull + kp - 1u) / kp);
@@ -161,12 +234,18 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
   uint32_t* stage = reinterpret_cast<uint32_t*>(smem + L.stage);
   uint32_t* csw = reinterpret_cast<uint32_t*>(smem + L.csize);  // class sizes, two 16-bit counts per word
   uint32_t* act = reinterpret_cast<uint32_t*>(smem + L.act);
-  int16_t* gcol = a.colors + (size_t)li * n;
+  uint32_t* sink = reinterpret_cast<uint32_t*>(smem + L.sink);
+  const gptr<int16_t> gcol = own_sgpr(a.colors + (size_t)li * n);
+  const gptr<const int32_t> erow = own_sgpr(a.erow);
   const __attribute__((address_space(4))) int32_t* row_c =
-      (const __attribute__((address_space(4))) int32_t*)a.row_ptr;
+      (const __attribute__((address_space(4))) int32_t*)(const int32_t*)own_sgpr(a.row_ptr);
+  // tie pass: LPR lanes per row (two dwords each), rpp rows per pass; this
+  // lane's row within a pass and its dword pair
+  const int lpr = (int)((kq + 1u) >> 1), rpp = kWave / lpr;
+  const int lrow = lane / lpr, lj = lane - lrow * lpr;
   auto csize = [&](uint32_t c) { return (csw[c >> 1] >> (16u * (c & 1u))) & 0xffffu; };
   auto give_up = [&]() {
-    if (lane == 0) a.iters[li] = -2;
+    if (lane == 0) *iters_out = -2;
   };
 
   // 1. start colouring (rejected whole if a colour is outside [0, k)), padded table, class sizes
@@ -178,8 +257,8 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
   }
   if (__ballot(bad)) {
     if (lane == 0) {
-      a.f_best[li] = -1;
-      a.iters[li] = -1;
+      *f_best_out = -1;
+      *iters_out = -1;
     }
     return;
   }
@@ -211,9 +290,9 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
     }
   }
   // 2. gamma from the CSR entries
-  const int nnz = a.row_ptr[n];
+  const int nnz = row_c[n];
   for (int e = lane; e < nnz; e += kWave) {
-    const uint32_t u = (uint32_t)col_idx[e], v = (uint32_t)a.erow[e];
+    const uint32_t u = (uint32_t)col_idx[e], v = (uint32_t)erow[e];
     const uint32_t c = cg[u];
     atomicAdd(&tabw[v * kq + (c >> 2)], 1u << (8u * (c & 3u)));
   }
@@ -230,34 +309,38 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
   int f = (int)(wave_sum_u32(fs) >> 1);
   wave_sync();
   int len = w8_build_list(cg, list, n, lane);
-  int stale = 0;
+  int C = len;  // conflicting vertices, as the last scan counted them
 
   int t = 0, f_best = f, A = 0;
   bool best_cur = true;
   uint32_t asp = kW8None;  // this lane's best biased delta among aspiring tabu pairs
-  // statistics and fingerprint live in lane 0; moves = t - no-ops
+  // statistics and fingerprint accumulate in lane 0 (vector registers, by
+  // select rather than branch: the scalar file is the scarce one); moves = t - no-ops
   uint64_t st_conf = 0, st_deg = 0, fp = kFnvOffset;
   uint32_t st_noops = 0, st_ties = 0, st_cap = 0;
+  const bool l0 = lane == 0;
   uint32_t Lreg = 0;
+  uint16_t* sink16 = reinterpret_cast<uint16_t*>(sink);
+  const W8RoundKeys rk = w8_round_keys(key);
 
   while (t < T && f > 0) {
-    if (((len + 63) >> 6) > ((len - stale + 63) >> 6)) {  // stale entries cost a scan round: rebuild
+    if (((len + 63) >> 6) > ((C + 64) >> 6)) {  // stale entries cost a scan round: compact
       wave_sync();
-      len = w8_build_list(cg, list, n, lane);
-      stale = 0;
+      len = w8_compact_list(cg, list, len, lane);
       wave_sync();
     }
-    const int C = len - stale;  // conflicting vertices
-    if ((t & 63) == 0) Lreg = lemire(philox_w0(ind, (uint32_t)(t + lane), 0u, kDomTenure, key), ten_rand);
+    if ((t & 63) == 0) Lreg = lemire(philox_w0_rk(ind, (uint32_t)(t + lane), 0u, kDomTenure, rk), ten_rand);
 
     // ---- scan: list entry (r << 6) + lane in round r
     const int rounds = (len + 63) >> 6;
     uint32_t best = kW8None, dlast = kW8None, vlast = (uint32_t)n, glast = 0u;
+    C = 0;
     for (int r = 0; r < rounds; ++r) {
       const int i = (r << 6) + lane;
       const uint32_t v = i < len ? (uint32_t)list[i] : (uint32_t)n;
       const uint32_t g = ((uint32_t)cg[v] >> 8) & 0x7fu;
-      const uint32_t* row = tabw + v * kq;
+      C += __popcll(__ballot(g != 0u));
+      const uint32_t* row = tabw + __umul24(v, kq);
       uint32_t w[KQ];
 #pragma unroll
       for (int q = 0; q < KQ; ++q) w[q] = row[q];
@@ -273,7 +356,7 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
       }
       const uint32_t m = min(min(ml & 0xffffu, ml >> 16), min(mh & 0xffffu, mh >> 16)) >> 8;
       const uint32_t d = (g != 0u && m < kW8Flag) ? m + 128u - g : kW8None;
-      if (i < len) rowkey[i] = (uint8_t)d;
+      if (rounds > 1) *(i < len ? rowkey + i : reinterpret_cast<uint8_t*>(sink)) = (uint8_t)d;
       best = min(best, d);
       dlast = d;
       vlast = v;
@@ -283,108 +366,98 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
     uint32_t key_star = kW8NoKey;  // the tabu pair a move onto a tabu colour consumes
 
     if (dstar == kW8None) {  // nothing admissible: no-op iteration
-      if (lane == 0) {
-        ++st_noops;
-        st_conf += (uint64_t)C;
-        fp = fnv_step(fp, 0xffffu, 0xffffu, f);
-        if (trace && t < trace_cap) {
-          gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
-          tr[0] = -1;
-          tr[1] = f;
-        }
+      st_noops += l0 ? 1u : 0u;
+      st_conf += l0 ? (uint64_t)C : 0ull;
+      fp = l0 ? fnv_step(fp, 0xffffu, 0xffffu, f) : fp;
+      if (trace && t < trace_cap && lane == 0) {
+        gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
+        tr[0] = -1;
+        tr[1] = f;
       }
     } else {
-      // ---- every admissible move at dstar: staged, hashed 64 at a time
-      int cnt = 0, total = 0;
+      // ---- every admissible move at dstar, hashed where it is found
+      // The rows at dstar are gathered into slots ((v << 8) | the byte value
+      // their best move has) and read again LPR lanes per row, two dwords
+      // per lane; tabu pairs at dstar come from the list.  Each lane hashes
+      // its own tied moves (Philox of (ind, t, v, c)) and keeps the smallest
+      // (hash, v, c).
       uint64_t hk = ~0ull;
-      auto flush64 = [&]() {
-        wave_sync();
-        const uint32_t e = stage[cnt - 64 + lane];
-        hk = umin64(hk, ((uint64_t)philox_w0(ind, (uint32_t)t, e >> 16, e & 0xffffu, key) << 32) | e);
-        cnt -= 64;
-        wave_sync();
-      };
-      auto put = [&](bool hit, uint32_t mv) {
-        const uint64_t mb = __ballot(hit);
-        if (hit) stage[cnt + (int)lane_rank(mb)] = mv;
-        cnt += __popcll(mb);
-        total += __popcll(mb);
-      };
-      const int jl = lane & (W - 1), pl = lane / W;
-      for (int r = 0; r < rounds; ++r) {
-        const bool lastr = r == rounds - 1;
-        const int i = (r << 6) + lane;
-        const uint32_t dr = lastr ? dlast : (i < len ? (uint32_t)rowkey[i] : kW8None);
-        uint64_t M = __ballot(dr == dstar);
-        while (M) {
-          // the next P tied rows: lane group pl takes row pl
-          uint32_t vsel = (uint32_t)n, tsel = 0u;
-#pragma unroll
-          for (int pp = 0; pp < P; ++pp) {
-            if (M) {
-              const int ln = __builtin_ctzll(M);
-              M &= M - 1;
-              uint32_t vr, gr;
-              if (lastr) {
-                vr = readlane(vlast, ln);
-                gr = readlane(glast, ln);
-              } else {
-                vr = rfl((uint32_t)list[(r << 6) + ln]);
-                gr = rfl(((uint32_t)cg[vr] >> 8) & 0x7fu);
-              }
-              if (pl == pp) {
-                vsel = vr;
-                tsel = dstar + gr - 128u;  // the row's smallest byte
-              }
-            }
+      uint32_t seen = 0;  // tied moves met so far, counted up to 2
+      // mask: bit 8 b + 7 set for a tie at colour c0 + b
+      auto hash_in = [&](uint64_t mask, uint32_t v, uint32_t c0) {
+        const uint64_t any = __ballot(mask != 0ull);
+        seen += (uint32_t)__popcll(any) + (__ballot(__popcll(mask) > 1) != 0ull ? 1u : 0u);
+        if (any == 0ull) return;
+        while (__ballot(mask != 0ull)) {
+          if (mask) {
+            const uint32_t c = c0 + ((uint32_t)__builtin_ctzll(mask) >> 3);
+            mask &= mask - 1ull;
+            hk = umin64(hk, ((uint64_t)philox_w0_rk(ind, (uint32_t)t, v, c, rk) << 32) | (v << 16) | c);
           }
-          const uint32_t x = jl < (int)kq ? tabw[vsel * kq + (uint32_t)jl] : 0xffffffffu;
-          const uint32_t y = x ^ (tsel * 0x01010101u);
-          // bit 7 of byte b set iff byte b of x equals tsel (tsel < 128, so
-          // flagged and padding bytes never match)
-          const uint32_t z = ~(((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y) & 0x80808080u;
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            put(((z >> (8 * b + 7)) & 1u) != 0u, (vsel << 16) | (uint32_t)(4 * jl + b));
-          while (cnt >= 64) flush64();
+        }
+      };
+      auto scan_slots = [&](int cnt) {
+        for (int p0 = 0; p0 < cnt; p0 += rpp) {
+          const int ri = p0 + lrow;
+          const bool ok = lrow < rpp && ri < cnt;
+          const uint32_t e0 = stage[ri];  // past cnt: harmless, replaced below
+          const uint32_t e = ok ? e0 : ((uint32_t)n << 8);  // row n: all padding, matches nothing
+          const uint32_t v = e >> 8, tv = (e & 0xffu) * 0x01010101u;
+          const uint32_t* rw = tabw + v * kq + 2u * (uint32_t)lj;
+          const uint32_t x0 = rw[0];
+          const uint32_t x1 = 2 * lj + 1 < (int)kq ? rw[1] : 0xffffffffu;
+          // bit 7 of byte b set iff byte b equals the target (a target is
+          // below 128, so flagged and padding bytes never match)
+          const uint32_t y0 = x0 ^ tv, y1 = x1 ^ tv;
+          const uint32_t z0 = ~(((y0 & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y0) & 0x80808080u;
+          const uint32_t z1 = ~(((y1 & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y1) & 0x80808080u;
+          hash_in((uint64_t)z0 | ((uint64_t)z1 << 32), v, 8u * (uint32_t)lj);
+        }
+      };
+      {
+        int nrows = 0;
+        for (int r = 0; r < rounds; ++r) {
+          const bool lastr = r == rounds - 1;
+          const int i = (r << 6) + lane;
+          uint32_t vr = vlast, gr = glast, dr = dlast;
+          if (!lastr) {
+            dr = i < len ? (uint32_t)rowkey[i] : kW8None;
+            vr = i < len ? (uint32_t)list[i] : (uint32_t)n;
+            gr = ((uint32_t)cg[vr] >> 8) & 0x7fu;
+          }
+          const bool tied = dr == dstar;
+          const uint64_t M = __ballot(tied);
+          *(tied ? stage + nrows + (int)lane_rank(M) : sink) = (vr << 8) | (dstar + gr - 128u);
+          nrows += __popcll(M);
+          if (nrows > kW8Stage - kWave || lastr) {
+            wave_sync();
+            scan_slots(nrows);
+            nrows = 0;
+            wave_sync();
+          }
         }
       }
       if (__ballot(asp == dstar)) {
         // tabu pairs at dstar: all of them aspire (the test depends on delta only)
         for (int i0 = 0; i0 < A; i0 += kWave) {
           const int i = i0 + lane;
-          bool hit = false;
-          uint32_t mv = 0u;
-          if (i < A) {
-            const uint32_t kk = act[i] >> 15;
-            const uint32_t v = __umulhi(kk, kp_inv), c = kk - v * kp;
-            const uint32_t g = ((uint32_t)cg[v] >> 8) & 0x7fu;
-            hit = g != 0u && (uint32_t)(tab[kk] & 0x7fu) + 128u - g == dstar;
-            mv = (v << 16) | c;
-          }
-          put(hit, mv);
-          while (cnt >= 64) flush64();
+          const uint32_t kk = i < A ? act[i] >> 15 : 0u;
+          const uint32_t v = __umulhi(kk, kp_inv), c = kk - v * kp;
+          const uint32_t g = ((uint32_t)cg[v] >> 8) & 0x7fu;
+          const bool hit = i < A && g != 0u && (uint32_t)(tab[kk] & 0x7fu) + 128u - g == dstar;
+          hash_in(hit ? 0x80ull : 0ull, v, c);
         }
       }
-      wave_sync();
-      uint32_t win;
-      if (total == 1) {
-        win = rfl(stage[0]);
-      } else {
-        if (lane < cnt) {
-          const uint32_t e = stage[lane];
-          hk = umin64(hk, ((uint64_t)philox_w0(ind, (uint32_t)t, e >> 16, e & 0xffffu, key) << 32) | e);
-        }
-        win = (uint32_t)wave_min_u64(hk);
-      }
+      const uint32_t win = (uint32_t)wave_min_u64(hk);
 
       // ---- apply (v*, c*)
       const uint32_t vs = win >> 16, cs = win & 0xffffu;
       const uint32_t xv = rfl((uint32_t)cg[vs]);
-      const uint32_t old = xv & 0xffu;
       const uint32_t bnew = rfl((uint32_t)tab[vs * kp + cs]);
+      const uint32_t csz = rfl(csize(cs));
+      const uint32_t old = xv & 0xffu;
       const int fnew = f + (int)dstar - 128;
-      if (rfl(csize(cs)) >= kW8ClassMax) {  // left to the 16-bit rerun
+      if (csz >= kW8ClassMax) {  // left to the 16-bit rerun
         give_up();
         return;
       }
@@ -395,54 +468,42 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
       const uint32_t dec = 0u - (1u << (8u * (old & 3u))), inc = 1u << (8u * (cs & 3u));
       const uint32_t wo = old >> 2, wn = cs >> 2;
       // neighbour u: gamma[u][old] - 1, gamma[u][c*] + 1; if u has colour old
-      // or c*, its own gamma and list membership follow
-      auto update = [&](uint32_t u, bool live) {
-        bool to_stale = false, from_stale = false, ins = false;
-        if (live) {
-          atomicAdd(&tabw[u * kq + wo], dec);
-          atomicAdd(&tabw[u * kq + wn], inc);
-          const uint32_t x = cg[u];
-          const uint32_t cu = x & 0xffu, g = (x >> 8) & 0x7fu;
-          if (cu == old) {
-            cg[u] = (uint16_t)(x - 0x100u);
-            to_stale = g == 1u;
-          } else if (cu == cs) {
-            if (g == 0u) {
-              from_stale = (x >> 15) != 0u;
-              ins = !from_stale;
-            }
-            cg[u] = (uint16_t)((x + 0x100u) | (ins ? 0x8000u : 0u));
-          }
+      // or c*, its own gamma and list membership follow.  Up to 256
+      // neighbours at a time: every CSR load issued before any is used, then
+      // every table add and cg read, then the cg updates; lanes past the row
+      // aim at the sink.
+      constexpr int kPre = 4;
+      for (int e0 = rs; e0 < re; e0 += kPre * kWave) {
+        uint32_t nb[kPre], xs[kPre];
+#pragma unroll
+        for (int r = 0; r < kPre; ++r)  // past the row: a copy of its last entry (valid, redirected below)
+          nb[r] = (uint32_t)col_idx[min(e0 + lane + r * kWave, re - 1)];
+#pragma unroll
+        for (int r = 0; r < kPre; ++r) {
+          const bool live = e0 + lane + r * kWave < re;
+          uint32_t* ru = tabw + __umul24(nb[r], kq);
+          atomicAdd(live ? ru + wo : sink, dec);
+          atomicAdd(live ? ru + wn : sink, inc);
+          xs[r] = cg[nb[r]];
         }
-        const uint64_t mi = __ballot(ins);
-        if (ins) list[len + (int)lane_rank(mi)] = (uint16_t)u;
-        len += __popcll(mi);
-        stale += __popcll(__ballot(to_stale)) - __popcll(__ballot(from_stale));
-      };
-      constexpr int kPre = 4;  // the first 256 neighbours: every load issued before any is used
-      int nb[kPre];
 #pragma unroll
-      for (int r = 0; r < kPre; ++r) {
-        const int e = rs + lane + r * kWave;
-        nb[r] = e < re ? col_idx[e] : -1;
+        for (int r = 0; r < kPre; ++r) {
+          if (e0 + r * kWave >= re) break;  // uniform: ballots see the whole wave
+          const bool live = e0 + lane + r * kWave < re;
+          const uint32_t x = xs[r], cu = x & 0xffu;
+          const bool lo = cu == old, hi = cu == cs;
+          // a neighbour that starts to conflict and is not listed yet is appended
+          const bool ins = live && hi && (x & 0xff00u) == 0u;
+          const uint32_t nx = x + (hi ? 0x100u : 0u) - (lo ? 0x100u : 0u) + (ins ? 0x8000u : 0u);
+          *(live ? &cg[nb[r]] : sink16) = (uint16_t)nx;
+          const uint64_t mi = __ballot(ins);
+          *(ins ? &list[len + (int)lane_rank(mi)] : sink16) = (uint16_t)nb[r];
+          len += __popcll(mi);
+        }
       }
-#pragma unroll
-      for (int r = 0; r < kPre; ++r)
-        if (rs + r * kWave < re) update((uint32_t)nb[r], nb[r] >= 0);
-      for (int e0 = rs + kPre * kWave; e0 < re; e0 += kWave) {
-        const int e = e0 + lane;
-        update(e < re ? (uint32_t)col_idx[e] : 0u, e < re);
-      }
-      // v*: its new colour flagged, its state, class sizes
+      // v*: its new colour flagged, its state, class sizes, the new tabu pair
       const uint32_t gnew = bnew & 0x7fu;
       if (bnew & kW8Flag) key_star = vs * kp + cs;  // a move onto a tabu colour: that pair is consumed
-      if (lane == 0) {
-        atomicOr(&tabw[vs * kq + wn], kW8Flag << (8u * (cs & 3u)));
-        cg[vs] = (uint16_t)(cs | (gnew << 8) | 0x8000u);
-        atomicAdd(&csw[old >> 1], 0u - (1u << (16u * (old & 1u))));
-        atomicAdd(&csw[cs >> 1], 1u << (16u * (cs & 1u)));
-      }
-      if (gnew == 0u) ++stale;
       // tenure term floor(num * f / den), capped (as in the block kernel)
       const uint64_t prod = (uint64_t)ten_num * (uint32_t)fnew;
       uint32_t ttf;
@@ -461,28 +522,32 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
       const bool capped = ttf > (uint32_t)kTenureCap;
       if (capped) ttf = kTenureCap;
       const uint32_t expiry = (uint32_t)t + readlane(Lreg, t & 63) + ttf;
-      if (expiry > (uint32_t)t + 1u) {  // tabu from iteration t + 1 on
-        if (A >= acap) {
-          give_up();
-          return;
-        }
-        if (lane == 0) act[A] = ((vs * kp + old) << 15) | (expiry & kW8ExpMask);
-        ++A;
-      } else if (lane == 0) {  // a tenure of 0 or 1 never forbids anything
-        atomicAnd(&tabw[vs * kq + wo], ~(kW8Flag << (8u * (old & 3u))));
+      const bool tabu_next = expiry > (uint32_t)t + 1u;  // tabu from iteration t + 1 on
+      if (tabu_next && A >= acap) {
+        give_up();
+        return;
       }
       if (lane == 0) {
-        if (trace && t < trace_cap) {
-          gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
-          tr[0] = (int32_t)(vs | (cs << 16));
-          tr[1] = fnew;
-        }
-        st_conf += (uint64_t)C;
-        st_deg += (uint64_t)(re - rs);
-        st_ties += total > 1 ? 1u : 0u;
-        st_cap += capped ? 1u : 0u;
-        fp = fnv_step(fp, vs, cs, fnew);
+        atomicOr(&tabw[vs * kq + wn], kW8Flag << (8u * (cs & 3u)));
+        cg[vs] = (uint16_t)(cs | (gnew << 8) | 0x8000u);
+        atomicAdd(&csw[old >> 1], 0u - (1u << (16u * (old & 1u))));
+        atomicAdd(&csw[cs >> 1], 1u << (16u * (cs & 1u)));
+        if (tabu_next)
+          act[A] = ((vs * kp + old) << 15) | (expiry & kW8ExpMask);
+        else  // a tenure of 0 or 1 never forbids anything
+          atomicAnd(&tabw[vs * kq + wo], ~(kW8Flag << (8u * (old & 3u))));
       }
+      if (tabu_next) ++A;
+      if (trace && t < trace_cap && lane == 0) {
+        gptr<int32_t> tr = trace + ((size_t)li * trace_cap + t) * 2;
+        tr[0] = (int32_t)(vs | (cs << 16));
+        tr[1] = fnew;
+      }
+      st_conf += l0 ? (uint64_t)C : 0ull;
+      st_deg += l0 ? (uint64_t)(re - rs) : 0ull;
+      st_ties += l0 && seen > 1u ? 1u : 0u;
+      st_cap += l0 && capped ? 1u : 0u;
+      fp = l0 ? fnv_step(fp, vs, cs, fnew) : fp;
       f = fnew;
       if (f < f_best) {
         f_best = f;
@@ -502,20 +567,18 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
       for (int i0 = 0; i0 < A; i0 += kWave) {
         const int i = i0 + lane;
         const bool alive = i < A;
-        const uint32_t e = alive ? act[i] : 0u;
+        const uint32_t e = act[alive ? i : 0];
         const uint32_t kk = e >> 15;
         const bool expired = alive && (e & kW8ExpMask) == ((uint32_t)t & kW8ExpMask);
         const bool drop = alive && kk == key_star;
-        if (expired && !drop) atomicAnd(&tabw[kk >> 2], ~(kW8Flag << (8u * (kk & 3u))));
+        atomicAnd(expired && !drop ? &tabw[kk >> 2] : sink, ~(kW8Flag << (8u * (kk & 3u))));
         const bool keep = alive && !expired && !drop;
-        if (keep && aspd >= -127) {
-          const uint32_t v = __umulhi(kk, kp_inv);
-          const int g = (int)(((uint32_t)cg[v] >> 8) & 0x7fu);
-          const int d = (int)(tab[kk] & 0x7fu) - g;
-          if (g != 0 && d <= aspd) asp = min(asp, (uint32_t)(d + 128));
-        }
+        const uint32_t v = __umulhi(kk, kp_inv);
+        const int g = (int)(((uint32_t)cg[v] >> 8) & 0x7fu);
+        const int d = (int)(tab[kk] & 0x7fu) - g;
+        if (keep && g != 0 && d <= aspd) asp = min(asp, (uint32_t)(d + 128));
         const uint64_t mk = __ballot(keep);
-        if (keep) act[base + (int)lane_rank(mk)] = e;
+        *(keep ? &act[base + (int)lane_rank(mk)] : sink) = e;
         base += __popcll(mk);
       }
       A = base;
@@ -526,10 +589,10 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
   if (best_cur)
     for (int v = lane; v < n; v += kWave) gcol[v] = (int16_t)(cg[v] & 0xffu);
   if (lane == 0) {
-    a.f_best[li] = f_best;
-    a.iters[li] = t;
-    if (a.stats) {
-      int64_t* s = a.stats + (size_t)li * DLM_NSTATS;
+    *f_best_out = f_best;
+    *iters_out = t;
+    if (stats_out) {
+      gptr<int64_t> s = stats_out;
       s[0] = (int64_t)(t - (int)st_noops);
       s[1] = (int64_t)st_noops;
       s[2] = (int64_t)st_conf;
@@ -539,7 +602,7 @@ __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, in
       s[6] = 0;
       s[7] = 0;
     }
-    if (a.hash) a.hash[li] = fp;
+    if (hash_out) *hash_out = fp;
   }
 }
 
