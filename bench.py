@@ -2,8 +2,9 @@
 
 Default workload (the configuration the headline metric is quoted on):
 G(500, 0.5) from seed 0, k = 49, population 8192, 100,000 tabu iterations
-per individual, byte gamma in LDS with 16-bit tabu expiries in device memory
-(four individuals resident per CU), 256 threads per workgroup.  One step = random population initialisation + one full TabuCol
+per individual, one wavefront per individual with everything in LDS: byte
+gamma whose top bit flags the current colour and tabu pairs, and a list of
+the live tabu pairs (five individuals resident per CU).  One step = random population initialisation + one full TabuCol
 pass over the population (every kernel of the search path); the graph is
 uploaded once, before timing.  Step s uses initial-colouring seed
 1 + s so every step searches new individuals.
@@ -31,8 +32,8 @@ import time
 
 import numpy as np
 
-GNP500_BLOCK = 256
-GNP500_TABLE = "split8"
+GNP500_BLOCK = 64
+GNP500_TABLE = "wave8"
 LDS_PEAK_GBS = 256 * 128 * 2.4  # GB/s: 256 CUs x 128 B/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 # 32-bit integer vector ops: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
@@ -44,8 +45,8 @@ METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned
 # --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads
 # for a 1 GiB device-to-device copy.  Valid only for the kernel sources they
 # were taken on (digest below) and the same table and block; otherwise null.
-MEASURED_TRAFFIC = {"sources_sha256": "cf4e5663af7ecbe6c68f5b9f43f23ce5679c2bae93ee9f4692b0252fc633a637",
-                    "table": "split8", "block": 256, "bytes": 84982992446}  # profiles/tabucol_split8_gnp500.md
+MEASURED_TRAFFIC = {"sources_sha256": "bb759d955db232e81063d38398727593835b11e7353571368dea2de559772c75",
+                    "table": "wave8", "block": 64, "bytes": 27147393}  # profiles/tabucol_wave8_gnp500.md
 KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd/csrc/tabucol.hip",
                   "paper_2109_05948_amd/csrc/dlm_common.h", "paper_2109_05948_amd/csrc/tabu_wave.h")
 

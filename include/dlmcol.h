@@ -119,7 +119,8 @@ int dlm_init_population(const dlm_graph* g, int32_t k, int32_t pop, uint64_t see
  *     L = floor(w0 * ten_rand / 2^32), w0 = Philox(seed; ind, t, 0, 0x80000001);
  *   the best colouring met (smallest f) is kept.
  * ---------------------------------------------------------------------- */
-#define DLM_TABLE_AUTO 0       /* LDS16 or SPLIT8, whichever keeps more workgroups per CU; GLOBAL16 if neither fits */
+#define DLM_TABLE_AUTO 0       /* WAVE8 when it holds the individual and block is 0 or 64; otherwise LDS16 or
+                                  SPLIT8, whichever keeps more workgroups per CU; GLOBAL16 if neither fits */
 #define DLM_TABLE_LDS16 1      /* 32-bit word per (v,c): gamma 16 bits | tabu 16 bits, LDS */
 #define DLM_TABLE_LDS32 2      /* 64-bit word per (v,c): gamma int32 | tabu expiry, LDS */
 #define DLM_TABLE_GLOBAL16 3   /* packed 16-bit words in device memory (large n*k) */
@@ -142,8 +143,9 @@ typedef struct dlm_tabu_params {
   int32_t ten_rand;   /* L uniform in [0, ten_rand), 1..1024 */
   int32_t ind_base;   /* global index of row 0 of the population */
   uint64_t seed;      /* Philox key */
-  int32_t block;      /* threads per workgroup: 0 = auto (256; 512 when AUTO storage fits only one
-                         individual per CU), else 64, 128, 256, 512 or 1024 */
+  int32_t block;      /* threads per workgroup: 0 = auto (64 with the WAVE8 table; otherwise 256, or
+                         512 when AUTO storage fits only one individual per CU), else 64, 128, 256,
+                         512 or 1024 (WAVE8 takes only 0 or 64) */
   int32_t table;      /* DLM_TABLE_* storage of the n x k table */
   int32_t trace_cap;  /* records per individual in trace_dev (0 = none) */
   int32_t reserved;   /* must be 0 */

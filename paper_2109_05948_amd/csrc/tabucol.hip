@@ -192,7 +192,13 @@ static int tabu_check(const char* fn, const dlm_graph* g, const dlm_tabu_params*
 static int tabu_plan(const char* fn, const dlm_graph* g, const dlm_tabu_params* p, int32_t pop, TabuPlan& P) {
   const int n = g->n, k = p->k;
   const int64_t lds_max = device_lds_limit();
-  if (p->table == DLM_TABLE_WAVE8) {
+  // automatic table with an automatic (or 64-thread) block: the wave table
+  // whenever it holds the individual (it beat the block kernels at every
+  // measured shape, one individual per CU included)
+  const bool wave_auto = p->table == DLM_TABLE_AUTO && (p->block == 0 || p->block == 64) && w8_bucket(k) != 0 &&
+                         (uint64_t)n * (uint64_t)tab_stride(k) <= (1ull << 17) &&
+                         w8_layout(n, k, 0).bytes + 4u * kWave <= (uint64_t)lds_max;
+  if (p->table == DLM_TABLE_WAVE8 || wave_auto) {
     if (p->block != 0 && p->block != 64)
       return set_error(DLM_E_INVAL, "%s: the wave table runs 64 threads per individual (block=%d)", fn, p->block);
     const uint64_t kp = (uint64_t)tab_stride(k);
