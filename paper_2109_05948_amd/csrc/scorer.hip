@@ -9,13 +9,13 @@
 //   y = h3 . w4 + b4                 LReLU(x) = max(0.2 x, x)
 //
 // H1 = 256, H2 = 128, H3 = 64.  Layer 2 and its two backward products run
-// on v_mfma_f32_32x32x8bf16_1k; layer 1 is a gather of FP32 W1 rows (a dense
+// on v_mfma_f32_32x32x16_bf16; layer 1 is a gather of FP32 W1 rows (a dense
 // one-hot product would cost n/k times more, and FP32 keeps the LeakyReLU
 // branch of a1 exact to FP32 rounding); the head is plain FP32.
 //
-// MFMA 32x32x8 (bf16) operand layout, lane l of a wave:
-//   A (32 x 8):  A[l % 32][4 (l / 32) + j], j = 0..3
-//   B (8 x 32):  B[4 (l / 32) + j][l % 32]
+// MFMA 32x32x16 (bf16) operand layout, lane l of a wave:
+//   A (32 x 16): A[l % 32][8 (l / 32) + j], j = 0..7
+//   B (16 x 32): B[8 (l / 32) + j][l % 32]
 //   D (32 x 32): D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32], r = 0..15
 #include <math.h>
 #include <string.h>
@@ -31,7 +31,7 @@ constexpr float kSlope = 0.2f;
 constexpr int kRowPadH1 = H1 + 8;  // LDS row stride (bf16) of h1, breaks bank aliasing
 constexpr int kRowPadH2 = H2 + 8;
 
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t f2bf(float x) {  // round to nearest even
@@ -44,11 +44,14 @@ __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint
 __device__ __forceinline__ float lrelu(float x) { return x > 0.f ? x : kSlope * x; }
 __device__ __forceinline__ float dlrelu(float h) { return h > 0.f ? 1.f : kSlope; }
 
-__device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) {
-  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+// gfx950's 32x32x16 BF16 MFMA: lane l supplies row l % 32 of A (of B^T)
+// with the eight K values 8 (l / 32) .. 8 (l / 32) + 7; the 32x32 FP32
+// result is spread as for every 32x32 MFMA (16 values per lane)
+__device__ __forceinline__ f16v mfma(bf8 a, bf8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ s4 ld_s4(const uint16_t* p) {  // 8-byte aligned
-  return *reinterpret_cast<const s4*>(p);
+__device__ __forceinline__ bf8 ld_b8(const uint16_t* p) {  // 16-byte aligned
+  return *reinterpret_cast<const bf8*>(p);
 }
 
 // Offsets (in floats) of the packed FP32 parameter vector.
@@ -166,10 +169,10 @@ __global__ __launch_bounds__(256) void scorer_fwd_kernel(ScorerDev s, const int1
   float zc = 0.f;  // this lane's share of z[n0 + lane % 32]
   for (int m0 = 0; m0 < kpad; m0 += 32) {
     f16v acc = {};
-    const uint16_t* arow = h1 + (m0 + (lane & 31)) * kRowPadH1 + 4 * (lane >> 5);
-    const uint16_t* brow = s.W2t + (size_t)(n0 + (lane & 31)) * H1 + 4 * (lane >> 5);
+    const uint16_t* arow = h1 + (m0 + (lane & 31)) * kRowPadH1 + 8 * (lane >> 5);
+    const uint16_t* brow = s.W2t + (size_t)(n0 + (lane & 31)) * H1 + 8 * (lane >> 5);
 #pragma unroll 4
-    for (int k0 = 0; k0 < H1; k0 += 8) acc = mfma(ld_s4(arow + k0), ld_s4(brow + k0), acc);
+    for (int k0 = 0; k0 < H1; k0 += 16) acc = mfma(ld_b8(arow + k0), ld_b8(brow + k0), acc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -256,10 +259,10 @@ __global__ __launch_bounds__(256) void scorer_bwd_kernel(ScorerDev s, const floa
     const int f0 = 32 * nt;
     for (int m0 = 0; m0 < kpad; m0 += 32) {
       f16v acc = {};
-      const uint16_t* arow = da2 + (m0 + (lane & 31)) * kRowPadH2 + 4 * (lane >> 5);
-      const uint16_t* brow = s.W2b + (size_t)(f0 + (lane & 31)) * H2 + 4 * (lane >> 5);
+      const uint16_t* arow = da2 + (m0 + (lane & 31)) * kRowPadH2 + 8 * (lane >> 5);
+      const uint16_t* brow = s.W2b + (size_t)(f0 + (lane & 31)) * H2 + 8 * (lane >> 5);
 #pragma unroll 4
-      for (int k0 = 0; k0 < H2; k0 += 8) acc = mfma(ld_s4(arow + k0), ld_s4(brow + k0), acc);
+      for (int k0 = 0; k0 < H2; k0 += 16) acc = mfma(ld_b8(arow + k0), ld_b8(brow + k0), acc);
       const int f = f0 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -288,12 +291,12 @@ __global__ __launch_bounds__(256) void scorer_dw2_kernel(int32_t count, int32_t 
   const int b_end = min(count, (c + 1) * kChunkB);
   for (int b = c * kChunkB; b < b_end; ++b) {
     const uint16_t* A = tb.h1t + (int64_t)b * H1 * kpad;
-    const uint16_t* B = tb.da2t + (int64_t)b * H2 * kpad + (int64_t)(q0 + (lane & 31)) * kpad + 4 * (lane >> 5);
-    for (int k0 = 0; k0 < kpad; k0 += 8) {
-      const s4 bf = ld_s4(B + k0);
+    const uint16_t* B = tb.da2t + (int64_t)b * H2 * kpad + (int64_t)(q0 + (lane & 31)) * kpad + 8 * (lane >> 5);
+    for (int k0 = 0; k0 < kpad; k0 += 16) {
+      const bf8 bf = ld_b8(B + k0);
 #pragma unroll
       for (int t = 0; t < 8; ++t)
-        acc[t] = mfma(ld_s4(A + (int64_t)(32 * t + (lane & 31)) * kpad + 4 * (lane >> 5) + k0), bf, acc[t]);
+        acc[t] = mfma(ld_b8(A + (int64_t)(32 * t + (lane & 31)) * kpad + 8 * (lane >> 5) + k0), bf, acc[t]);
     }
   }
   float* out = tb.part + (int64_t)c * H1 * H2;
@@ -526,7 +529,8 @@ int dlm_scorer_create(int32_t n, int32_t k, int32_t h1, int32_t h2, int32_t h3, 
   s->tb.part = f; f += nchunk * H1 * H2;
   s->tb.p1 = f; f += B * H1;
   s->tb.p2 = f; f += B * H2;
-  uint16_t* h = (uint16_t*)f;
+  // the BF16 region starts on a 16-byte boundary: its rows are read 8 values at a time
+  uint16_t* h = (uint16_t*)(((uintptr_t)f + 15) & ~(uintptr_t)15);
   s->W2b = h; h += H1 * H2;
   s->W2t = h; h += H1 * H2;
   s->tb.h1t = h; h += B * H1 * kp;
