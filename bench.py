@@ -165,8 +165,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gnp500",
                     choices=["gnp500", "gnp100", "uneven64", "wvcp300", "memetic1000", "scorer", "diversity",
-                             "decreasing", "popsweep", "invnet", "predict"])
-    ap.add_argument("--pops", default="256,1024,4096,16384", help="popsweep: population sizes")
+                             "decreasing", "popsweep", "invnet", "predict", "gemm"])
+    ap.add_argument("--pops", default="100,400,1600,6400,25600,51200", help="popsweep: population sizes")
+    ap.add_argument("--sweep-graph", default="wvcp500", choices=["wvcp500", "wvcp300"],
+                    help="popsweep: the weighted graph")
     ap.add_argument("--passes", type=int, default=3,
                     help="popsweep: budget = this many local-search passes of the largest population")
     ap.add_argument("--cutoff", type=float, default=300.0,
@@ -184,9 +186,6 @@ def main():
                     help="memetic1000: training epochs per generation (default: the workload's)")
     ap.add_argument("--generations", type=int, default=16, help="predict: generations per loop")
     ap.add_argument("--eval-chunk", type=int, default=2048, help="invnet: colourings per evaluation pass")
-    ap.add_argument("--tune", type=int, default=0,
-                    help="invnet, predict, memetic1000: choose the GEMM solutions of the colour-invariant "
-                         "network by measurement before timing (1) or keep the library's defaults (0)")
     ap.add_argument("--block", type=int, default=GNP500_BLOCK)
     ap.add_argument("--table", default=GNP500_TABLE)
     ap.add_argument("--pop", type=int, default=0, help="override the population (testing only)")
@@ -225,10 +224,12 @@ def main():
         return bench_diversity(args, workload("gnp500"), dlm, torch)
     if args.workload == "invnet":
         return bench_invnet(args, workload("gnp500"), dlm, torch)
+    if args.workload == "gemm":
+        return bench_gemm(args, workload("gnp500"), dlm, torch)
     if args.workload == "predict":
         return bench_predict(args, workload("wvcp300"), dlm, torch)
     if args.workload == "popsweep":
-        return bench_popsweep(args, workload("wvcp300"), workload("memetic1000"), dlm, torch)
+        return bench_popsweep(args, workload(args.sweep_graph), workload("memetic1000"), dlm, torch)
     if args.workload == "decreasing":
         return bench_decreasing(args, workload("gnp500"), workload("memetic1000"), dlm, torch)
     w = workload(args.workload)
@@ -452,8 +453,7 @@ def bench_memetic(args, w, dlm, torch):
                             cutoff_s=args.cutoff, children_per_pair=e["children_per_pair"],
                             keep_frac=e["keep_frac"], scorer_params=params, batch=batch, epochs=epochs,
                             lr=e["lr"], log=log, diversity=args.diversity > 0,
-                            neighbours=max(args.diversity, 1), network=args.network,
-                            tune_gemms=bool(args.tune))
+                            neighbours=max(args.diversity, 1), network=args.network)
             runs.append({"seed": sd, "time_to_legal_s": r.time_to_legal, "best_f": r.best,
                          "generations": r.generations, "wall_s": r.wall,
                          "tabu_moves_per_s": r.tabu_moves / r.wall,
@@ -538,40 +538,43 @@ def bench_scorer(args, w, dlm, torch):
 def bench_popsweep(args, w, wm, dlm, torch):
     """Sensitivity to the population size at a fixed total number of local-
     search iterations (the study of the paper's Section 4 on the WVCP): the
-    learned memetic loop on the weighted G(300, 0.3) of wvcp300, greedy
-    start, 10 rounds of 10 n iterations per local search, for each
-    population p as many generations as the budget allows (budget = passes
-    x the largest p local searches).  Reports the best legal weighted score
-    reached by each p and its trajectory."""
+    learned memetic loop on the weighted G(500, 0.5) of wvcp500 (the shape of
+    the paper's DSJC500.5 study), greedy start, 10 rounds of 10 n iterations
+    per local search, for each population p and each seed as many
+    generations as the budget allows (budget = passes x the largest p local
+    searches; the largest p gets passes - 1 generations).  Reports the best
+    legal weighted score reached by each (p, seed) and its trajectory."""
     from paper_2109_05948_amd import memetic
     from workloads.scorer_init import scorer_weights
     g = w.graphs[0]
     G = dlm.Graph.from_csr(g)
     pops = [int(x) for x in args.pops.split(",")]
+    seeds = [int(x) for x in args.seeds.split(",")]
     per_search = 10 * g.n * 10
     budget = args.passes * max(pops) * per_search
     e = wm.extra
     out_runs = []
     for p in pops:
         passes = budget // (p * per_search)
-        log(f"popsweep p={p}: {passes} local-search passes ({passes - 1} generations)")
-        r = memetic.run(G, 0, p, 10 * g.n, learned=True, seed=int(args.seeds.split(",")[0]),
-                        cutoff_s=args.cutoff, max_generations=max(passes - 1, 0),
-                        children_per_pair=e["children_per_pair"], keep_frac=e["keep_frac"],
-                        scorer_params=scorer_weights(g.n, seed=0), batch=min(e["batch"], p),
-                        epochs=e["epochs"], lr=e["lr"], weighted=True, rounds=10, log=log,
-                        diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
-        out_runs.append({"population": p, "generations": r.generations, "best_wscore": r.best,
-                         "wall_s": r.wall, "moves": r.tabu_moves,
-                         "history": [[h[0], h[1], h[2]] for h in r.history]})
-        log(f"popsweep p={p}: best {r.best} after {r.generations} generations, {r.wall:.1f} s")
+        for sd in seeds:
+            log(f"popsweep p={p} seed={sd}: {passes} local-search passes ({passes - 1} generations)")
+            r = memetic.run(G, 0, p, 10 * g.n, learned=True, seed=sd,
+                            cutoff_s=args.cutoff, max_generations=max(passes - 1, 0),
+                            children_per_pair=e["children_per_pair"], keep_frac=e["keep_frac"],
+                            scorer_params=scorer_weights(g.n, seed=0), batch=min(e["batch"], p),
+                            epochs=e["epochs"], lr=e["lr"], weighted=True, rounds=10, log=log,
+                            diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
+            out_runs.append({"population": p, "seed": sd, "generations": r.generations,
+                             "best_wscore": r.best, "wall_s": r.wall, "moves": r.tabu_moves,
+                             "history": [[h[0], h[1], h[2]] for h in r.history]})
+            log(f"popsweep p={p} seed={sd}: best {r.best} after {r.generations} generations, {r.wall:.1f} s")
     best = min(out_runs, key=lambda x: (x["best_wscore"], x["population"]))
     out = {"metric": "best legal weighted score at a fixed tabu budget vs population size (lower is better)",
            "value": best["best_wscore"], "unit": "weighted score", "n_gpus": 1, "higher_is_better": False,
            "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-           "config": {"workload": "popsweep", "graph": "G(n=300, p=0.3) seed 0, weights U{1..100}",
-                      "populations": pops, "iters_per_search": per_search, "budget_iters": budget,
-                      "best_population": best["population"]},
+           "config": {"workload": "popsweep", "graph": f"{w.name}: G(n={g.n}) weights U{{1..100}}",
+                      "populations": pops, "seeds": seeds, "iters_per_search": per_search,
+                      "budget_iters": budget, "best_population": best["population"]},
            "runs": out_runs}
     print(json.dumps(out), flush=True)
 
@@ -712,7 +715,8 @@ def bench_invnet(args, w, dlm, torch):
     colourings and standard-normal targets, resident before timing; weights
     from the seeded fully connected initialisation.
 
-    Every product is a BF16 GEMM with FP32 accumulation (rocBLAS); the rest
+    Every product is a BF16 GEMM with FP32 accumulation (the library's MFMA
+    kernel, dlm_gemm_bf16); the rest
     (one-hot input, class means, normalisation, activation, loss, Adam) runs
     on the library's kernels.  The roofline is the dense BF16 MFMA peak."""
     from workloads.invnet_init import col_widths, invnet_weights
@@ -727,11 +731,6 @@ def bench_invnet(args, w, dlm, torch):
     tgt = torch.randn(p, generator=gen).to("cuda")
     scores = torch.empty(p, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
-    if args.tune:
-        t_ = time.perf_counter()
-        for b_ in sorted({batch, chunk, p % batch, p % chunk} - {0}):
-            net.tune(b_)
-        log(f"GEMM solutions tuned in {time.perf_counter() - t_:.1f} s")
     for s_ in range(args.warmup):
         log(f"warmup step {s_}")
         net.forward(col, out=scores)
@@ -760,8 +759,7 @@ def bench_invnet(args, w, dlm, torch):
            "warmup": args.warmup, "ms_per_step": dt * 1e3 / max(args.steps, 1), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16+fp32", "data": "synthetic",
            "config": {"workload": "invnet", "graph": "G(n=500, p=0.5) seed 0", "k": k, "widths": widths,
-                      "colourings": p, "batch": batch, "eval_chunk": chunk, "epochs": 1,
-                      "gemm_solutions": "tuned" if args.tune else "default"},
+                      "colourings": p, "batch": batch, "eval_chunk": chunk, "epochs": 1},
            "inference_ms": inf_ms, "train_epoch_ms": tr_ms,
            "train_pairs_per_s": p / (tr_ms * 1e-3),
            "roofline": {"bound": "mfma", "achieved": inf_tf, "peak": 2500.0, "unit": "TFLOP/s",
@@ -769,6 +767,89 @@ def bench_invnet(args, w, dlm, torch):
                         "flops_per_colouring": inf_f / p, "train_achieved": tr_tf,
                         "train_frac": tr_tf / 2500.0, "train_flops_per_pair": tr_f / p}}
     print(json.dumps(out), flush=True)
+
+def gemm_shapes(n, k, widths, chunk, batch):
+    """Every product of the network's scoring chunk and training step:
+    (name, a_kcontig, b_kcontig, M, N, K, calls per chunk or step)."""
+    out, l_in = [], n
+    for j, l_out in enumerate(widths[:-1]):
+        out.append((f"score rows L{j}", True, False, chunk * k, l_out, l_in, 1))
+        out.append((f"score mean L{j}", True, False, chunk, l_out, l_in, 1))
+        out.append((f"train rows L{j}", True, False, batch * k, l_out, l_in, 1))
+        out.append((f"train mean L{j}", True, False, batch, l_out, l_in, 1))
+        out.append((f"train at L{j}", False, False, l_in, l_out, batch * k, 1))
+        out.append((f"train at-mean L{j}", False, False, l_in, l_out, batch, 1))
+        if j > 0:
+            out.append((f"train wt L{j}", True, True, batch * k, l_in, l_out, 1))
+            out.append((f"train wt-mean L{j}", True, True, batch, l_in, l_out, 1))
+        l_in = l_out
+    return out
+
+
+def bench_gemm(args, w, dlm, torch):
+    """The network's products alone (the paper-depth k-COL network for
+    G(500, 0.5), k = 49: scoring chunks of --eval-chunk colourings, training
+    batches of 100), each timed with dlm_gemm_bf16 (FP32 output) and, for
+    context, with torch.mm on the same BF16 operands (the vendor BLAS, BF16
+    output).  Reports TFLOP/s per product and flop-weighted totals for a
+    scoring chunk and a training step."""
+    g, k = w.graphs[0], w.k[0]
+    from workloads.invnet_init import col_widths
+    widths = col_widths(g.n)
+    shapes = gemm_shapes(g.n, k, widths, args.eval_chunk, 100)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    reps = max(args.steps, 1)
+    ws = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")  # split-K partials
+    rows = []
+    tot = {"score": [0.0, 0.0, 0.0], "train": [0.0, 0.0, 0.0]}
+    for name, ak, bk, M, N, K, calls in shapes:
+        A = torch.randn((M, K) if ak else (K, M), device="cuda", generator=gen).to(torch.bfloat16)
+        B = torch.randn((N, K) if bk else (K, N), device="cuda", generator=gen).to(torch.bfloat16)
+        C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        At = A if ak else A.t()
+        Bt = B.t() if bk else B
+        def ours():
+            dlm.gemm_bf16(A, B, M, N, K, ak, bk, out=C, workspace=ws)
+        def lib():
+            torch.mm(At, Bt)
+        res = []
+        for fn in (ours, lib):
+            for _ in range(max(args.warmup, 1)):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res.append(e0.elapsed_time(e1) / reps)
+        fl = 2.0 * M * N * K * calls
+        part = tot["score" if name.startswith("score") else "train"]
+        part[0] += fl
+        part[1] += res[0] * 1e-3
+        part[2] += res[1] * 1e-3
+        rows.append({"product": name, "M": M, "N": N, "K": K, "ms": res[0], "tflops": fl / res[0] / 1e9,
+                     "torch_mm_ms": res[1], "torch_mm_tflops": fl / res[1] / 1e9})
+        log(f"{name:>18s} {M:>6d} x {N:>5d} x {K:>6d}: {res[0]:8.3f} ms {fl / res[0] / 1e9:6.0f} TFLOP/s"
+            f" | torch.mm {res[1]:8.3f} ms {fl / res[1] / 1e9:6.0f} TFLOP/s")
+        del A, B, C
+    summary = {kk: {"tflops": v[0] / v[1] / 1e12, "ms": v[1] * 1e3, "torch_mm_tflops": v[0] / v[2] / 1e12,
+                    "torch_mm_ms": v[2] * 1e3} for kk, v in tot.items()}
+    for kk, v in summary.items():
+        log(f"{kk}: {v['ms']:.2f} ms, {v['tflops']:.0f} TFLOP/s (torch.mm {v['torch_mm_ms']:.2f} ms, "
+            f"{v['torch_mm_tflops']:.0f} TFLOP/s)")
+    tf = summary["train"]["tflops"]
+    print(json.dumps({"metric": "BF16 MFMA product throughput (paper-depth network, training step)",
+                      "value": tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+fp32",
+                      "data": "synthetic",
+                      "config": {"workload": "gemm", "widths": widths, "k": k, "eval_chunk": args.eval_chunk,
+                                 "batch": 100},
+                      "roofline": {"bound": "mfma", "achieved": tf, "peak": 2500.0, "unit": "TFLOP/s",
+                                   "frac": tf / 2500.0, "traffic": None, "kernel": "gemm_bf16_kernel"},
+                      "summary": summary, "products": rows}), flush=True)
+
 
 def bench_predict(args, w, dlm, torch):
     """The paper's analysis of its network (Section 4.2) on the weighted
@@ -803,7 +884,7 @@ def bench_predict(args, w, dlm, torch):
             r = memetic.run(G, 0, pop, w.iters[0], learned=net != "plain", seed=sd, cutoff_s=args.cutoff,
                             max_generations=args.generations, scorer_params=params, batch=batch, epochs=5,
                             lr=1e-3, diversity=True, neighbours=32, weighted=True, rounds=w.extra["rounds"],
-                            network="invariant" if net == "invariant" else "mlp", tune_gemms=bool(args.tune))
+                            network="invariant" if net == "invariant" else "mlp")
             runs.append({"seed": sd, "generations": r.generations, "wall_s": r.wall,
                          "best_per_generation": [h[2] for h in r.history],
                          "predictions": [{"gen": gg, "pearson": pr, "median_rel_err_pct": re}

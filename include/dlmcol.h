@@ -551,7 +551,7 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * learnable scale gamma_j and shift mu_j per feature, running estimates with
  * momentum 0.1 and the unbiased variance); the last layer has width 1 and
  * the output is (1/k) sum_i Z_i.  The hidden layers' products are GEMMs with
- * BF16 operands and FP32 accumulation (rocBLAS); the output layer's products
+ * BF16 operands and FP32 accumulation (dlm_gemm_bf16); the output layer's products
  * and everything else run in FP32 on kernels of this library, reductions in
  * a fixed order.
  *
@@ -565,14 +565,14 @@ int dlm_scorer_train(dlm_scorer* s, const int16_t* colors_dev, const float* targ
  * (max_batch k) n bytes).  2 <= k <= 32767, n <= 32767, max_batch <= 65535,
  * max_batch k < 2^31.
  * ---------------------------------------------------------------------- */
-/* Calls on one network share its activation buffers and rocBLAS handles:
+/* Calls on one network share its activation buffers and streams:
  * they must not overlap (one stream, or ordered by the caller).  Each call
  * is ordered on the stream it is given: the network's second stream forks
  * from it and joins it again before the call returns.  Use a network on the
  * device that was current at its creation.  Errors return a
  * negative code with a message from dlm_last_error(); device buffers belong
  * to the caller, the network owns its own memory until dlm_invnet_destroy. */
-typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, rocBLAS handle */
+typedef struct dlm_invnet dlm_invnet; /* opaque: weights, Adam state, activations, second stream */
 
 int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, const float* params_host,
                       int32_t max_batch, dlm_invnet** out);
@@ -613,17 +613,30 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors_dev, const float* targ
                      int32_t batch, int32_t epochs, float lr, float* loss_dev, void* stream);
 
 /*
- * Choose the GEMM kernels of the network by measurement: for every product
- * of a training pass at `batch` colourings (forward and backward; the
- * evaluation of a chunk of that size uses the forward ones), time each
- * solution the GEMM library lists for the call, and its default choice, on
- * `stream`, and use the fastest from then on.  Shapes not tuned keep the
- * default.  Synchronises the stream; the trial launches write only the
- * network's scratch buffers.  The choice depends on timing and so may differ
- * between runs and machines; every solution accumulates in FP32, but the
- * summation order (and so the last bits) can differ from the default's.
+ * The network's matrix product on its own (Section 2.3: the layer products
+ * X Lambda and R Gamma, their weight gradients X^T dZ and input gradients
+ * dZ Lambda^T), exposed so that it can be checked and timed alone:
+ *   C[m][n] = sum_{k < K} A(m, k) B(k, n)   for m < M, n < N,
+ * A(m, k) = A_dev[m sa + k] if a_kcontig else A_dev[k sa + m],
+ * B(k, n) = B_dev[n sb + k] if b_kcontig else B_dev[k sb + n],
+ * A and B BF16 (raw 16-bit patterns), C FP32 row-major with pitch ldc >= N;
+ * products accumulate in FP32 (MFMA 32x32x16).  K = 0 writes zeros; M or
+ * N = 0 does nothing.  Any pitch and alignment work; pitches and pointers
+ * that are multiples of 4 values (8 bytes) read fastest.
+ * tile: 0 picks the workgroup tile (64, 128 or 256 square) from the shape,
+ * else that tile.  splits: 0 picks from the shape whether to cut K into
+ * chunks (when the tile grid is too small to fill the device), else that
+ * many chunks; chunk s writes its partial product into workspace_dev
+ * (float[splits][M][N], caller-owned, used only when splits > 1 and it is
+ * large enough; may be NULL) and a second kernel adds the partials in chunk
+ * order.  The result depends only on the shape, the tile and the split, so
+ * repeated calls give identical bits.  Errors: negative sizes, ldc < N, a
+ * pitch smaller than its contiguous extent, a bad tile, a forced split
+ * without room, or a null operand.  Asynchronous on stream.
  */
-int dlm_invnet_tune(dlm_invnet* s, int32_t batch, void* stream);
+int dlm_gemm_bf16(int32_t a_kcontig, const uint16_t* A_dev, int64_t sa, int32_t b_kcontig, const uint16_t* B_dev,
+                  int64_t sb, float* C_dev, int64_t ldc, int32_t M, int32_t N, int32_t K, int32_t tile,
+                  int32_t splits, void* workspace_dev, int64_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Measurement helper (not part of the search): sustained LDS read bandwidth

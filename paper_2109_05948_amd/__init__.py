@@ -14,6 +14,7 @@ from ._abi import (  # noqa: F401
     abi_version,
     evaluate,
     gather_distances,
+    gemm_bf16,
     gather_pool,
     gather_rows,
     nearest,

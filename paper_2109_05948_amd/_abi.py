@@ -37,7 +37,7 @@ EXPORTS = [
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
     "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours", "dlm_invnet_create",
     "dlm_invnet_destroy", "dlm_invnet_num_params", "dlm_invnet_get_params", "dlm_invnet_forward",
-    "dlm_invnet_grad", "dlm_invnet_train", "dlm_invnet_tune",
+    "dlm_invnet_grad", "dlm_invnet_train", "dlm_gemm_bf16",
 ]
 
 
@@ -108,7 +108,7 @@ def lib():
             L.dlm_invnet_forward.argtypes = [P, P, I32, P, P]
             L.dlm_invnet_grad.argtypes = [P, P, P, I32, P, P, P]
             L.dlm_invnet_train.argtypes = [P, P, P, I32, I32, I32, C.c_float, P, P]
-            L.dlm_invnet_tune.argtypes = [P, I32, P]
+            L.dlm_gemm_bf16.argtypes = [I32, P, I64, I32, P, I64, P, I64, I32, I32, I32, I32, I32, P, I64, P]
             for name in EXPORTS:
                 getattr(L, name)
             _lib = L
@@ -488,10 +488,6 @@ class InvNet:
 
     score = forward  # the scorer interface of the memetic loop
 
-    def tune(self, batch: int, stream=None):
-        """dlm_invnet_tune: pick the fastest GEMM solutions for passes of `batch` colourings."""
-        _check("dlm_invnet_tune", lib().dlm_invnet_tune(self._h, batch, _stream(stream)))
-
     def grad(self, colors: torch.Tensor, targets: torch.Tensor, stream=None):
         """dlm_invnet_grad -> (flat FP32 gradient of the batch MSE, loss)."""
         _dev(colors, torch.int16, "colors")
@@ -762,6 +758,34 @@ class MultiBatch:
             self.close()
         except Exception:
             pass
+
+
+def gemm_bf16(a: torch.Tensor, b: torch.Tensor, m: int, n: int, k: int, a_kcontig: bool, b_kcontig: bool,
+              sa: int | None = None, sb: int | None = None, out: torch.Tensor | None = None, ldc: int | None = None,
+              tile: int = 0, splits: int = 0, workspace: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """dlm_gemm_bf16: C[m][n] = sum_k A(m, k) B(k, n) in FP32 from BF16 (or
+    raw int16) operands.  A(m, k) = a[m sa + k] if a_kcontig else a[k sa + m];
+    B(k, n) = b[n sb + k] if b_kcontig else b[k sb + n]; the pitches default
+    to the contiguous extents.  ``workspace`` (any contiguous CUDA tensor)
+    holds split-K partials; a forced ``splits`` > 1 without one gets a fresh
+    buffer.  Returns out (float32 [m][ldc])."""
+    for t, nm in ((a, "a"), (b, "b")):
+        if t.dtype not in (torch.bfloat16, torch.int16) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous bfloat16 or int16 CUDA tensor")
+    sa = sa if sa is not None else (k if a_kcontig else m)
+    sb = sb if sb is not None else (k if b_kcontig else n)
+    ldc = ldc if ldc is not None else n
+    if out is None:
+        out = torch.empty((m, ldc), dtype=torch.float32, device=a.device)
+    _dev(out, torch.float32, "out")
+    if out.numel() < m * ldc:
+        raise ValueError("out is smaller than m * ldc")
+    if workspace is None and splits > 1:
+        workspace = torch.empty(splits * m * n, dtype=torch.float32, device=a.device)
+    wptr, wbytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
+    _check("dlm_gemm_bf16", lib().dlm_gemm_bf16(int(a_kcontig), _ptr(a), sa, int(b_kcontig), _ptr(b), sb, _ptr(out),
+                                                ldc, m, n, k, tile, splits, wptr, wbytes, _stream(stream)))
+    return out
 
 
 def probe_lds_bandwidth(rounds: int = 2000, stream=None) -> float:

@@ -51,9 +51,7 @@ def build(verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + f".tmp{os.getpid()}"
-    # rocBLAS serves the plain GEMMs of the colour-invariant network
-    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     os.replace(tmp, OUT)
     if verbose:

@@ -150,6 +150,20 @@ int device_lds_limit();  // max dynamic LDS bytes per workgroup on the current d
 int device_cu_count();
 int device_lds_per_cu();  // LDS bytes of one CU on the current device
 
+// BF16 x BF16 -> FP32 MFMA product on stream s (gemm.hip):
+// C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sa + k] if a_kcontig else
+// A[k sa + m], B(k, n) = B[n sb + k] if b_kcontig else B[k sb + n];
+// tile / splits 0 pick the workgroup tile and the K split from the shape; a
+// split writes its partials to ws (splits M N floats).
+struct GemmPlan {
+  int tile, splits;
+};
+GemmPlan gemm_plan(int M, int N, int K, int vec, int64_t ws_bytes, int tile, int splits);
+int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, const uint16_t* B, int64_t sb, float* C,
+              int64_t ldc, int M, int N, int K, int tile, int splits, void* ws, int64_t ws_bytes, hipStream_t s);
+// workspace a product of this shape can use (its split partials), in bytes
+int64_t gemm_workspace_bytes(int M, int N, int K);
+
 #define DLM_HIP(call)                                    \
   do {                                                   \
     hipError_t e_ = (call);                              \

@@ -8,17 +8,11 @@
 //            statistics in training, running estimates with momentum 0.1 in
 //            evaluation; learnable scale and shift per feature)
 //   output (width 1):  f = class mean of Z.
-// The products of the hidden layers are plain GEMMs (BF16 operands, FP32
-// accumulation and output) and go to rocBLAS; the width-1 output layer's
+// The products of the hidden layers are GEMMs (BF16 operands, FP32
+// accumulation and output) on the MFMA kernels of gemm.hip; the width-1 output layer's
 // products (matrix-vector, FP32 weights), the one-hot input, class means,
 // broadcasts, normalisation, activation, loss, their backward steps and
 // Adam are the kernels below.  All reductions run in a fixed order.
-#define ROCBLAS_BETA_FEATURES_API  // solution listing for measured GEMM choice
-#define ROCBLAS_NO_DEPRECATED_WARNINGS
-#include <rocblas/rocblas.h>
-
-#include <map>
-#include <tuple>
 #include <vector>
 
 #include "dlm_common.h"
@@ -620,114 +614,39 @@ struct dlm_invnet {
   float *dX = nullptr, *dR = nullptr, *df = nullptr, *fout = nullptr;
   float *pa = nullptr, *pb = nullptr;  // per-colouring partial sums [B][lmax]
   uint16_t *dZb = nullptr, *dUb = nullptr;
+  // split-K partials of the products on each stream (they run concurrently)
+  void *gw = nullptr, *gw_side = nullptr;
+  int64_t gw_bytes = 0, gw_side_bytes = 0;
   int adam_t = 0;
   void* ws = nullptr;
-  rocblas_handle h = nullptr;
-  // GEMM solution per (transA, transB, m, n, k), chosen by dlm_invnet_tune;
-  // shapes not in the map use the library's default choice
-  std::map<std::tuple<int, int, int, int, int>, int32_t> solution;
-  bool tuning = false;
-  hipStream_t tune_stream = nullptr;
+  hipStream_t stream = nullptr;  // the stream of the call in progress
   // the class-mean products (one row per colouring) run on a second stream,
   // beside the class-row products of the same layer
   hipStream_t side = nullptr;
-  rocblas_handle h_side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
 
-rocblas_status gemm_call(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                         const void* A, int lda, const void* B, int ldb, float beta, float* C, int ldc,
-                         int32_t sol) {
-  const float alpha = 1.f;
-  return rocblas_gemm_ex(h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B, rocblas_datatype_bf16_r,
-                         ldb, &beta, C, rocblas_datatype_f32_r, ldc, C, rocblas_datatype_f32_r, ldc,
-                         rocblas_datatype_f32_r, sol >= 0 ? rocblas_gemm_algo_solution_index : rocblas_gemm_algo_standard,
-                         sol >= 0 ? sol : 0, 0);
-}
-
-// time every solution rocBLAS lists for this call (and its default) on the
-// tuning stream and keep the fastest; the call's buffers are the network's
-// own scratch, so the trial launches change nothing that persists
-int tune_gemm(dlm_invnet* s, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A, int lda,
-              const void* B, int ldb, float beta, float* C, int ldc) {
-  const auto key = std::make_tuple((int)ta, (int)tb, m, n, k);
-  if (s->solution.count(key)) return DLM_OK;
-  const float alpha = 1.f;
-  rocblas_int cnt = 0;
-  if (rocblas_gemm_ex_get_solutions(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B,
-                                    rocblas_datatype_bf16_r, ldb, &beta, C, rocblas_datatype_f32_r, ldc, C,
-                                    rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
-                                    rocblas_gemm_algo_solution_index, 0, nullptr, &cnt) != rocblas_status_success)
-    cnt = 0;
-  std::vector<rocblas_int> list((size_t)cnt);
-  if (cnt > 0 &&
-      rocblas_gemm_ex_get_solutions(s->h, ta, tb, m, n, k, &alpha, A, rocblas_datatype_bf16_r, lda, B,
-                                    rocblas_datatype_bf16_r, ldb, &beta, C, rocblas_datatype_f32_r, ldc, C,
-                                    rocblas_datatype_f32_r, ldc, rocblas_datatype_f32_r,
-                                    rocblas_gemm_algo_solution_index, 0, list.data(), &cnt) != rocblas_status_success)
-    cnt = 0;
-  list.resize((size_t)cnt);
-  list.insert(list.begin(), -1);  // the default choice
-  hipEvent_t e0, e1;
-  DLM_HIP(hipEventCreate(&e0));
-  DLM_HIP(hipEventCreate(&e1));
-  float best = 1e30f;
-  int32_t pick = -1;
-  for (int32_t sol : list) {
-    if (gemm_call(s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) != rocblas_status_success) continue;
-    constexpr int kReps = 3;
-    (void)hipEventRecord(e0, s->tune_stream);
-    bool ok = true;
-    for (int r = 0; r < kReps && ok; ++r)
-      ok = gemm_call(s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol) == rocblas_status_success;
-    (void)hipEventRecord(e1, s->tune_stream);
-    if (hipEventSynchronize(e1) != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      return set_error(DLM_E_HIP, "dlm_invnet_tune: event synchronisation failed");
-    }
-    float ms = 0.f;
-    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
-      best = ms;
-      pick = sol;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  s->solution[key] = pick;
-  return DLM_OK;
-}
-
-// side: issue on the second stream (a class-mean product)
-int gemm(dlm_invnet* s, bool side, rocblas_operation ta, rocblas_operation tb, int m, int n, int k, const void* A,
-         int lda, const void* B, int ldb, float beta, float* C, int ldc) {
-  if (s->tuning) return tune_gemm(s, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc);
-  const auto it = s->solution.find(std::make_tuple((int)ta, (int)tb, m, n, k));
-  const int32_t sol = it == s->solution.end() ? -1 : it->second;
-  const rocblas_status st = gemm_call(side ? s->h_side : s->h, ta, tb, m, n, k, A, lda, B, ldb, beta, C, ldc, sol);
-  if (st != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_gemm_ex failed (%d)", (int)st);
-  return DLM_OK;
-}
-
-// row-major C[rows][cols] = A[rows][inner] W[inner][cols]  (column-major: C^T = W^T A^T)
+// the products run on the network's current stream, the class-mean ones
+// (side) on its second stream
+// row-major C[rows][cols] = A[rows][inner] W[inner][cols]
 int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, int rows, int inner, int cols, float* C,
             bool side = false) {
-  return gemm(s, side, rocblas_operation_none, rocblas_operation_none, cols, rows, inner, W, cols, A, inner, 0.f, C,
-              cols);
+  return gemm_bf16(true, A, inner, false, W, cols, C, cols, rows, cols, inner, 0, 0, side ? s->gw_side : s->gw,
+                   side ? s->gw_side_bytes : s->gw_bytes, side ? s->side : s->stream);
 }
 // row-major C[inner][cols] = A[rows][inner]^T D[rows][cols]
 int mm_at(dlm_invnet* s, const uint16_t* A, const uint16_t* D, int rows, int inner, int cols, float* C,
           bool side = false) {
-  return gemm(s, side, rocblas_operation_none, rocblas_operation_transpose, cols, inner, rows, D, cols, A, inner, 0.f,
-              C, cols);
+  return gemm_bf16(false, A, inner, false, D, cols, C, cols, inner, cols, rows, 0, 0, side ? s->gw_side : s->gw,
+                   side ? s->gw_side_bytes : s->gw_bytes, side ? s->side : s->stream);
 }
 // row-major C[rows][inner] = D[rows][cols] W[inner][cols]^T
 int mm_wt(dlm_invnet* s, const uint16_t* D, const uint16_t* W, int rows, int inner, int cols, float* C,
           bool side = false) {
-  return gemm(s, side, rocblas_operation_transpose, rocblas_operation_none, inner, rows, cols, W, cols, D, cols, 0.f,
-              C, inner);
+  return gemm_bf16(true, D, cols, true, W, cols, C, inner, rows, inner, cols, 0, 0, side ? s->gw_side : s->gw,
+                   side ? s->gw_side_bytes : s->gw_bytes, side ? s->side : s->stream);
 }
 
 // the side stream starts after everything issued on st so far; st later
@@ -852,7 +771,7 @@ int inv_refresh_bf16(dlm_invnet* s, hipStream_t st) {
 }
 
 int set_stream(dlm_invnet* s, hipStream_t st) {
-  if (rocblas_set_stream(s->h, st) != rocblas_status_success) return set_error(DLM_E_HIP, "rocblas_set_stream failed");
+  s->stream = st;
   return DLM_OK;
 }
 
@@ -968,6 +887,19 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
   parts.push_back({(void**)&s->fout, 4 * B});
   parts.push_back({(void**)&s->dZb, 2 * N * lmax});
   parts.push_back({(void**)&s->dUb, 2 * B * lmax});
+  // the weight gradients X^T dZ (K = the batch's class rows) may cut K into
+  // chunks when their tile grid is small; size both streams' partials
+  for (int j = 0; j + 1 < nl; ++j) {
+    const int li = s->lin[j], lo = s->lout[j];
+    s->gw_bytes = std::max(s->gw_bytes, gemm_workspace_bytes(li, lo, (int)N));
+    s->gw_bytes = std::max(s->gw_bytes, gemm_workspace_bytes((int)N, lo, li));
+    if (j > 0) s->gw_bytes = std::max(s->gw_bytes, gemm_workspace_bytes((int)N, li, lo));
+    s->gw_side_bytes = std::max(s->gw_side_bytes, gemm_workspace_bytes(li, lo, (int)B));
+    s->gw_side_bytes = std::max(s->gw_side_bytes, gemm_workspace_bytes((int)B, lo, li));
+    if (j > 0) s->gw_side_bytes = std::max(s->gw_side_bytes, gemm_workspace_bytes((int)B, li, lo));
+  }
+  parts.push_back({&s->gw, std::max<int64_t>(s->gw_bytes, 256)});
+  parts.push_back({&s->gw_side, std::max<int64_t>(s->gw_side_bytes, 256)});
   int64_t bytes = 0;
   for (auto& p : parts) bytes += (p.second + 255) & ~255ll;
   hipError_t e = hipMalloc(&s->ws, (size_t)bytes);
@@ -980,16 +912,9 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
     *p.first = (unsigned char*)s->ws + off;
     off += (p.second + 255) & ~255ll;
   }
-  if (rocblas_create_handle(&s->h) != rocblas_status_success) {
-    (void)hipFree(s->ws);
-    delete s;
-    return set_error(DLM_E_HIP, "rocblas_create_handle failed");
-  }
   if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess ||
-      rocblas_create_handle(&s->h_side) != rocblas_status_success ||
-      rocblas_set_stream(s->h_side, s->side) != rocblas_status_success) {
+      hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess) {
     dlm_invnet_destroy(s);
     return set_error(DLM_E_HIP, "dlm_invnet_create: second stream set-up failed");
   }
@@ -1012,8 +937,6 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
 int dlm_invnet_destroy(dlm_invnet* s) {
   if (!s) return DLM_OK;
   if (s->side) (void)hipStreamSynchronize(s->side);
-  if (s->h_side) rocblas_destroy_handle(s->h_side);
-  if (s->h) rocblas_destroy_handle(s->h);
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   if (s->side) (void)hipStreamDestroy(s->side);
@@ -1082,30 +1005,6 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets,
       DLM_HIP(hipGetLastError());
       ++step;
     }
-  return rc;
-}
-
-int dlm_invnet_tune(dlm_invnet* s, int32_t batch, void* stream) {
-  if (!s || batch < 1 || batch > s->max_batch)
-    return set_error(DLM_E_INVAL, "dlm_invnet_tune: batch=%d (need 1..max_batch)", batch);
-  hipStream_t st = (hipStream_t)stream;
-  int rc = set_stream(s, st);
-  if (rc != DLM_OK) return rc;
-  const int B = batch, N = batch * s->k;
-  s->tuning = true;
-  s->tune_stream = st;
-  // every product of a training pass (forward and backward) at this batch;
-  // evaluation uses the forward ones
-  for (int j = 0; rc == DLM_OK && j + 1 < s->nl; ++j) {
-    const int li = s->lin[j], lo = s->lout[j];
-    rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], N, li, lo, s->Z[j]);
-    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j]);
-    if (rc == DLM_OK) rc = mm_at(s, s->X[j], s->dZb, N, li, lo, s->Gr + s->oL[j]);
-    if (rc == DLM_OK) rc = mm_at(s, s->R[j], s->dUb, B, li, lo, s->Gr + s->oG[j]);
-    if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dZb, s->Pb + s->oLb[j], N, li, lo, s->dX);
-    if (rc == DLM_OK && j > 0) rc = mm_wt(s, s->dUb, s->Pb + s->oGb[j], B, li, lo, s->dR);
-  }
-  s->tuning = false;
   return rc;
 }
 

@@ -95,8 +95,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         epochs: int = 5, lr: float = 1e-3, block: int = 0, table: str = "auto",
         log=None, diversity: bool = False, neighbours: int = 16,
         init_colors: torch.Tensor | None = None, weighted: bool = False, rounds: int = 10,
-        target: int | None = None, network: str = "mlp", eval_chunk: int = 1024,
-        tune_gemms: bool = False) -> MemeticResult:
+        target: int | None = None, network: str = "mlp", eval_chunk: int = 1024) -> MemeticResult:
     """One loop of Algorithm 1.  With ``weighted`` it solves the WVCP
     (Section 2.2): the start is the greedy colouring (k = 0 takes the largest
     number of colours it uses), the local search is Algorithm 2 with
@@ -111,8 +110,7 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
     "invariant" is the paper's colour-invariant network of Section 2.3
     (dlm_invnet, ``scorer_params`` its weights with a "widths" entry),
     trained at ``batch`` colourings per step and evaluated in chunks of
-    ``eval_chunk``; ``tune_gemms`` lets it pick its GEMM kernels by
-    measurement first (dlm_invnet_tune)."""
+    ``eval_chunk``."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if target is None:
         target = -1 if weighted else 0
@@ -160,9 +158,6 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         sc = A.Scorer(graph.n, k, scorer_params, max_batch=batch)
     elif learned:
         sc = A.InvNet(graph.n, k, scorer_params["widths"], scorer_params, max_batch=max(batch, eval_chunk))
-        if tune_gemms:  # the training batches (pop pairs) and the scoring chunks (nchild offspring)
-            for b in sorted({batch, eval_chunk, pop % batch, nchild % eval_chunk} - {0}):
-                sc.tune(b)
     off = torch.empty((nsel, graph.n), dtype=torch.int16, device=dev)
     start = torch.empty_like(off)
     if diversity:

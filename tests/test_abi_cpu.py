@@ -137,5 +137,23 @@ def test_invnet_argument_checks(L):
     assert L.dlm_invnet_grad(None, None, None, 1, None, None, None) == -1
     assert L.dlm_invnet_train(None, None, None, 1, 1, 1, C.c_float(1e-3), None, None) == -1
     assert L.dlm_invnet_get_params(None, None, None) == -1
-    assert L.dlm_invnet_tune(None, 1, None) == -1
     assert L.dlm_invnet_destroy(None) == 0
+
+
+def test_gemm_argument_checks(L):
+    """dlm_gemm_bf16 refuses bad shapes, pitches, tiles, splits and null
+    operands before touching the device; an empty output is a no-op."""
+    a = C.c_void_p(16)
+    c = C.c_void_p(16)
+    g = L.dlm_gemm_bf16
+    assert g(1, a, 8, 0, a, 8, c, 8, -1, 8, 8, 0, 0, None, 0, None) == -1  # negative M
+    assert g(1, a, 8, 0, a, 8, c, 4, 8, 8, 8, 0, 0, None, 0, None) == -1  # ldc < N
+    assert g(1, a, 8, 0, a, 8, c, 8, 8, 8, 8, 96, 0, None, 0, None) == -1  # tile not 0/64/128/256
+    assert g(1, None, 8, 0, a, 8, c, 8, 8, 8, 8, 0, 0, None, 0, None) == -1  # null A
+    assert g(1, a, 4, 0, a, 8, c, 8, 8, 8, 8, 0, 0, None, 0, None) == -1  # K-contiguous pitch < K
+    assert g(0, a, 4, 0, a, 8, c, 8, 8, 8, 8, 0, 0, None, 0, None) == -1  # M-contiguous pitch < M
+    assert g(1, a, 8, 0, a, 8, c, 8, 8, 8, 8, 0, 4, None, 0, None) == -1  # forced split, no workspace
+    assert g(1, a, 8, 0, a, 8, c, 8, 8, 8, 8, 0, 4, a, 100, None) == -1  # forced split, workspace too small
+    assert g(1, a, 8, 0, a, 8, c, 8, 8, 8, 8, 0, 65, a, 1 << 20, None) == -1  # more than 64 splits
+    assert g(1, a, 1 << 23, 0, a, 8, c, 8, 8, 8, 8, 0, 0, None, 0, None) == -1  # pitch above 2^22
+    assert g(1, None, 8, 0, None, 8, None, 8, 0, 8, 8, 0, 0, None, 0, None) == 0  # M = 0: nothing to do

@@ -287,23 +287,25 @@ def test_paper_depth_sampled(dlm, dev):
     close(got[idx], want, dv["f"], "paper depth, chunks of 2048")
 
 
-def test_tuned_products(dlm, dev):
-    """After the GEMM solutions are chosen by measurement (training batch and
-    evaluation chunk), evaluation and gradients still follow the oracle."""
-    n, k, widths, b = 130, 7, [200, 70, 70, 1], 24
+def test_odd_widths_repeatable(dlm, dev):
+    """Odd widths (every product takes single-value operand pieces) follow the
+    oracle, and a second evaluation and gradient repeat the first bit for bit
+    (the products accumulate in a fixed order)."""
+    n, k, widths, b = 131, 7, [201, 71, 69, 1], 24
     rng = np.random.default_rng(21)
     colors = rng.integers(0, k, size=(b, n)).astype(np.int16)
     targets = rng.normal(0, 1, size=b).astype(np.float32)
     P = f32(calibrated(params(n, widths, 22), colors, k, 23))
-    say("invnet tuned products")
+    say("invnet odd widths, repeated calls")
     net = dlm.InvNet(n, k, widths, P, max_batch=b)
-    net.tune(b)
-    net.tune(b // 3)
     got = net.forward(cuda(colors)).cpu().numpy()
+    assert np.array_equal(got, net.forward(cuda(colors)).cpu().numpy())
     want, _ = ref.forward(P, colors, k, train=False)
     dv = deviation(lambda q: {"f": ref.forward(P, colors, k, train=False, q=q)[0]}, {"f": want})
-    close(got, want, dv["f"], "tuned forward")
+    close(got, want, dv["f"], "odd-width forward")
     g, _ = net.grad(cuda(colors), cuda(targets))
+    g2, _ = net.grad(cuda(colors), cuda(targets))
+    assert torch.equal(g, g2)
     g = net.unpack(g.cpu().numpy(), net.train_names)
 
     def run(q):
