@@ -13,6 +13,8 @@ DIMACS/COLOR instances), with every seed fixed.
   G(1000, 0.5), k=85, population 8192.  Shape of DSJC1000.5.
 * ``wvcp300``  : weighted coloring, G(300, 0.3), weights uniform on
   [1, 100], population 4096, 10 rounds of 10*n tabu iterations.
+* ``wvcp500``  : weighted coloring, G(500, 0.5), weights uniform on
+  [1, 100]: the graph of the population-size study.
 """
 from __future__ import annotations
 
@@ -87,12 +89,23 @@ def _wvcp300() -> Workload:
                     ten_num=2, ten_den=10, extra={"rounds": 10, "k_cap": 60})
 
 
+def _wvcp500() -> Workload:
+    # stand-in for the paper's DSJC500.5 weighted-colouring study of the
+    # population size: G(500, 0.5), weights uniform on [1, 100]
+    g = gnp(500, 0.5, seed=0)
+    w = uniform_weights(500, 1, 100, seed=7)
+    g = g.with_weights(w)
+    return Workload("wvcp500", [g], [0], 4096, [10 * 500],
+                    ten_num=2, ten_den=10, extra={"rounds": 10})
+
+
 WORKLOADS = {
     "gnp100": _gnp100,
     "gnp500": _gnp500,
     "uneven64": _uneven64,
     "memetic1000": _memetic1000,
     "wvcp300": _wvcp300,
+    "wvcp500": _wvcp500,
 }
 
 
