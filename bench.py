@@ -773,10 +773,11 @@ def gemm_shapes(n, k, widths, chunk, batch):
     (name, a_kcontig, b_kcontig, M, N, K, calls per chunk or step)."""
     out, l_in = [], n
     for j, l_out in enumerate(widths[:-1]):
-        out.append((f"score rows L{j}", True, False, chunk * k, l_out, l_in, 1))
-        out.append((f"score mean L{j}", True, False, chunk, l_out, l_in, 1))
-        out.append((f"train rows L{j}", True, False, batch * k, l_out, l_in, 1))
-        out.append((f"train mean L{j}", True, False, batch, l_out, l_in, 1))
+        # forward products read Lambda^T / Gamma^T: both operands K-contiguous
+        out.append((f"score rows L{j}", True, True, chunk * k, l_out, l_in, 1))
+        out.append((f"score mean L{j}", True, True, chunk, l_out, l_in, 1))
+        out.append((f"train rows L{j}", True, True, batch * k, l_out, l_in, 1))
+        out.append((f"train mean L{j}", True, True, batch, l_out, l_in, 1))
         out.append((f"train at L{j}", False, False, l_in, l_out, batch * k, 1))
         out.append((f"train at-mean L{j}", False, False, l_in, l_out, batch, 1))
         if j > 0:

@@ -370,6 +370,203 @@ __global__ __launch_bounds__(THREADS) void gemm_bf16_kernel(const uint16_t* __re
     }
 }
 
+// 16 bytes per lane from global memory straight into LDS (lane l writes LDS
+// bytes [16 l, 16 l + 16) past L).  The builtin only exists for the device;
+// the host pass, which only needs the kernel's launch stub, sees nothing.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DLM_LDS_DIRECT16(G, L) __builtin_amdgcn_global_load_lds((G), (L), 16, 0, 0)
+#else
+#define DLM_LDS_DIRECT16(G, L) ((void)(G), (void)(L))
+#endif
+
+// One step of the direct kernel from its swizzled LDS image.  Fragments
+// live in two register sets (fa, fb)[2] that persist across steps: slices
+// alternate between them, so a step ends with its last slice in set 1,
+// whose MFMAs run at the start of the next step and cover the latency of
+// that step's first fragment reads (set 0) across the barrier between the
+// steps.  NV direct reads of the next step, issued just before the call,
+// are spread over the first MFMAs.
+template <int TM, int NV>
+__device__ __forceinline__ void mma_direct(const uint16_t* sA, const uint16_t* sB, int wm, int wn, int lr, int lh,
+                                           f16v (&acc)[TM][TM], bf8 (&fa)[2][TM], bf8 (&fb)[2][TM]) {
+  static_assert(KS % 2 == 0, "the last slice of a step lands in set 1");
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int ra = wm + 32 * i + lr, rb = wn + 32 * i + lr;
+    fa[0][i] = *reinterpret_cast<const bf8*>(sA + ra * BKT + 8 * (lh ^ (ra & 7)));
+    fb[0][i] = *reinterpret_cast<const bf8*>(sB + rb * BKT + 8 * (lh ^ (rb & 7)));
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[1][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int c = ks & 1;
+    if (ks + 1 < KS) {
+      const int ch = 2 * (ks + 1) + lh;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int ra = wm + 32 * i + lr, rb = wn + 32 * i + lr;
+        fa[c ^ 1][i] = *reinterpret_cast<const bf8*>(sA + ra * BKT + 8 * (ch ^ (ra & 7)));
+        fb[c ^ 1][i] = *reinterpret_cast<const bf8*>(sB + rb * BKT + 8 * (ch ^ (rb & 7)));
+      }
+    }
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[c][i], fb[c][j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // schedule: this step's first fragment reads; the carried slice's MFMAs
+  // with the NV direct reads spread over them; then each slice's MFMAs with
+  // the next slice's reads spread over them
+  constexpr int NMS = TM * TM, NRS = 2 * TM;  // MFMAs and fragment reads per slice
+  __builtin_amdgcn_sched_group_barrier(0x100, NRS, 0);
+#pragma unroll
+  for (int m = 0; m < NMS; ++m) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    const int nv = (m + 1) * NV / NMS - m * NV / NMS;
+#pragma unroll
+    for (int j = 0; j < nv; ++j) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+  }
+#pragma unroll
+  for (int ks = 0; ks + 1 < KS; ++ks)
+#pragma unroll
+    for (int m = 0; m < NMS; ++m) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      const int nr = (m + 1) * NRS / NMS - m * NRS / NMS;
+#pragma unroll
+      for (int j = 0; j < nr; ++j) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+}
+
+// Both operands K-contiguous with 16-byte aligned rows: the reads go from
+// global memory straight to LDS (16 bytes per lane, no registers, no LDS
+// write instructions).  One such read fills 1 KB of LDS in lane order, 8
+// rows of 64 k; each row is 8 chunks of 16 bytes stored at chunk c ^ (row % 8),
+// so that the 16-byte operand reads of 8 neighbouring rows hit distinct
+// banks.  Step s + 1 is read into the other buffer while step s runs (four
+// separate LDS arrays, the loop unrolled by two, so that the compiler sees
+// the reads and the buffer being written apart); a wait and a barrier end
+// each step.  Windowed only (the reads stay inside the operands); where a
+// step's window overlaps k already summed, those chunks are zeroed in LDS
+// before the barrier.  An odd step count runs one step past the end, which
+// is all zeros.
+template <int TM>
+__global__ __launch_bounds__(THREADS) void gemm_direct_kernel(const uint16_t* __restrict__ A, int64_t sa,
+                                                              const uint16_t* __restrict__ B, int64_t sb,
+                                                              float* __restrict__ C, int64_t ldc, int M, int N, int K,
+                                                              int tiles_n, int kchunk, float* __restrict__ W) {
+  constexpr int T = 64 * TM;
+  __shared__ __align__(16) uint16_t sA0[T * BKT];
+  __shared__ __align__(16) uint16_t sA1[T * BKT];
+  __shared__ __align__(16) uint16_t sB0[T * BKT];
+  __shared__ __align__(16) uint16_t sB1[T * BKT];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int m0 = (t / tiles_n) * T, n0 = (t % tiles_n) * T;
+  const int mr = min(m0, M - T), nr = min(n0, N - T);
+  const int wm = (wid >> 1) * 32 * TM, wn = (wid & 1) * 32 * TM;
+  const int lr = lane & 31, lh = lane >> 5;
+  const int kbeg = (int)blockIdx.y * kchunk;
+  const int Kl = min(K - kbeg, kchunk);
+  A += kbeg;
+  B += kbeg;
+  if (gridDim.y > 1) {
+    C = W + (int64_t)blockIdx.y * M * N;
+    ldc = N;
+  }
+  f16v acc[TM][TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = f16v{};
+  // lane's place in a 1 KB group: row lane / 8, LDS chunk lane % 8, which
+  // holds source chunk (lane % 8) ^ (row % 8)
+  const int grow = lane >> 3, gch = (lane & 7) ^ (grow & 7);
+  const uint16_t* pa = A + (int64_t)(mr + grow) * sa + 8 * gch;
+  const uint16_t* pb = B + (int64_t)(nr + grow) * sb + 8 * gch;
+  constexpr int GPW = T / 32;  // 8-row groups per wave and operand
+  const int nk = (Kl + BKT - 1) / BKT;
+#define DLM_DIRECT_ISSUE(SA_, SB_, STEP)                                                                   \
+  do {                                                                                                     \
+    const int kb_ = min((STEP) * BKT, Kl - BKT);                                                           \
+    _Pragma("unroll") for (int g = 0; g < GPW; ++g) {                                                      \
+      const int grp = wid + 4 * g;                                                                          \
+      DLM_LDS_DIRECT16(pa + (int64_t)(8 * grp) * sa + kb_, SA_ + grp * 8 * BKT);                    \
+      DLM_LDS_DIRECT16(pb + (int64_t)(8 * grp) * sb + kb_, SB_ + grp * 8 * BKT);                    \
+    }                                                                                                      \
+  } while (0)
+  // after the step's reads have landed in every wave: zero the chunks below
+  // lo (k already summed, everything past the end) of both operands
+#define DLM_DIRECT_MASK(SA_, SB_, STEP)                                                   \
+  do {                                                                                   \
+    const int k0_ = (STEP) * BKT, kb_ = min(k0_, Kl - BKT);                              \
+    if (k0_ > kb_) {                                                                     \
+      __syncthreads(); /* every wave's reads have landed before any chunk is zeroed */   \
+      const int nch_ = min((k0_ - kb_) / 8, 8);                                          \
+      for (int e_ = tid; e_ < T * nch_; e_ += THREADS) {                                 \
+        const int r_ = e_ / nch_, c_ = e_ % nch_;                                        \
+        const int off_ = r_ * BKT + 8 * (c_ ^ (r_ & 7));                                 \
+        *reinterpret_cast<uint4*>(SA_ + off_) = make_uint4(0u, 0u, 0u, 0u);              \
+        *reinterpret_cast<uint4*>(SB_ + off_) = make_uint4(0u, 0u, 0u, 0u);              \
+      }                                                                                  \
+    }                                                                                    \
+  } while (0)
+  if (nk > 0) {
+    DLM_DIRECT_ISSUE(sA0, sB0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    DLM_DIRECT_MASK(sA0, sB0, 0);
+  }
+  __syncthreads();
+  // fragment sets; set 1 (the carried last slice) starts as zeros, whose
+  // MFMAs add nothing
+  bf8 fa[2][TM], fb[2][TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    fa[1][i] = bf8{};
+    fb[1][i] = bf8{};
+  }
+  for (int kt = 0; kt < nk; kt += 2) {
+    DLM_DIRECT_ISSUE(sA1, sB1, kt + 1);
+    mma_direct<TM, 2 * GPW>(sA0, sB0, wm, wn, lr, lh, acc, fa, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's reads of the next step have landed
+    DLM_DIRECT_MASK(sA1, sB1, kt + 1);
+    __syncthreads();
+    DLM_DIRECT_ISSUE(sA0, sB0, kt + 2);
+    mma_direct<TM, 2 * GPW>(sA1, sB1, wm, wn, lr, lh, acc, fa, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    DLM_DIRECT_MASK(sA0, sB0, kt + 2);
+    __syncthreads();
+  }
+  // the last step's last slice
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[1][j], acc[i][j], 0, 0, 0);
+#undef DLM_DIRECT_ISSUE
+#undef DLM_DIRECT_MASK
+  // tile (i, j): value r of lane l is C[32 i + 8 (r / 4) + 4 (l / 32) + r % 4][32 j + l % 32]
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      const int n = nr + wn + 32 * j + lr;
+      if (n < n0) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mr + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m >= m0) C[(int64_t)m * ldc + n] = acc[i][j][r];
+      }
+    }
+}
+
 // C[m][n] = sum over s = 0 .. S-1 (in that order) of W[s][m][n]
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(const float* __restrict__ W, int S, int M, int N,
                                                           float* __restrict__ C, int64_t ldc) {
@@ -407,6 +604,16 @@ void launch_vec(bool ak, bool bk, dim3 grid, hipStream_t s, const uint16_t* A, i
   else
     hipLaunchKernelGGL((gemm_bf16_kernel<TM, false, true, VEC, WIN>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C,
                        ldc, M, N, K, tn, kchunk, W);
+}
+
+void launch_direct(int tile, dim3 grid, hipStream_t s, const uint16_t* A, int64_t sa, const uint16_t* B, int64_t sb,
+                   float* C, int64_t ldc, int M, int N, int K, int tn, int kchunk, float* W) {
+  if (tile == 256)
+    hipLaunchKernelGGL((gemm_direct_kernel<4>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+  else if (tile == 128)
+    hipLaunchKernelGGL((gemm_direct_kernel<2>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+  else
+    hipLaunchKernelGGL((gemm_direct_kernel<1>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
 }
 
 // the windowed kernels need 2- or 4-value pieces, a whole tile of rows in
@@ -492,6 +699,13 @@ int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, con
   const dim3 grid((unsigned)nt, (unsigned)Sg);
   float* W = (float*)ws;
   const bool win = gemm::windowed(M, N, K, vec, p.tile);
+  // both operands K-contiguous with 16-byte aligned rows and K steps: the
+  // direct-to-LDS kernel
+  const bool direct = win && a_kcontig && b_kcontig && K % 8 == 0 && sa % 8 == 0 && sb % 8 == 0 &&
+                      reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+  if (direct) {
+    gemm::launch_direct(p.tile, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+  } else {
 #define DLM_GEMM_LAUNCH(TM, V, WIN) \
   gemm::launch_vec<TM, V, WIN>(a_kcontig, b_kcontig, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W)
   if (p.tile == 256) {
@@ -518,6 +732,7 @@ int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, con
       DLM_GEMM_LAUNCH(1, 1, false);
   }
 #undef DLM_GEMM_LAUNCH
+  }
   DLM_HIP(hipGetLastError());
   if (Sg > 1) {
     const int64_t MN = (int64_t)M * N;

@@ -591,6 +591,24 @@ __global__ __launch_bounds__(256) void inv_to_bf16_kernel(const float* __restric
   if (e < count) dst[e] = to_bf16(src[e]);
 }
 
+// dst[c][r] = src[r][c] for a rows x cols BF16 matrix: a 64 x 64 tile per
+// workgroup through LDS (the hidden layers' Lambda^T and Gamma^T, which make
+// both operands of the forward products K-contiguous)
+__global__ __launch_bounds__(256) void inv_transpose_kernel(const uint16_t* __restrict__ src, int32_t rows,
+                                                            int32_t cols, uint16_t* __restrict__ dst) {
+  __shared__ uint16_t t[64][66];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (r0 + r < rows && c0 + c < cols) t[r][c] = src[(int64_t)(r0 + r) * cols + c0 + c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    if (r0 + r < rows && c0 + c < cols) dst[(int64_t)(c0 + c) * rows + r0 + r] = t[r][c];
+  }
+}
+
 }  // namespace dlm
 
 using namespace dlm;
@@ -605,6 +623,9 @@ struct dlm_invnet {
   int64_t total = 0, nrun = 0;
   float *P = nullptr, *M = nullptr, *V = nullptr, *Gr = nullptr, *run = nullptr;
   uint16_t* Pb = nullptr;  // BF16 copies of every L and G
+  uint16_t* PbT = nullptr;  // BF16 Lambda^T and Gamma^T of the hidden layers ([l_out][l_in])
+  bool t_fresh = false;     // PbT matches Pb (refreshed after training, not after every Adam step)
+  std::vector<int64_t> oLT, oGT;  // their offsets (multiples of 8 values)
   // activations for max_batch colourings
   std::vector<uint16_t*> X;  // X[j]: BF16 [N][lin[j]]
   std::vector<uint16_t*> R;  // R[j]: BF16 [B][lin[j]]
@@ -630,9 +651,14 @@ namespace {
 
 // the products run on the network's current stream, the class-mean ones
 // (side) on its second stream
-// row-major C[rows][cols] = A[rows][inner] W[inner][cols]
-int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, int rows, int inner, int cols, float* C,
-            bool side = false) {
+// row-major C[rows][cols] = A[rows][inner] W[inner][cols]: from WT = W^T
+// [cols][inner] when the transposed copies are fresh (both operands
+// K-contiguous), else from W
+int mm_rows(dlm_invnet* s, const uint16_t* A, const uint16_t* W, const uint16_t* WT, int rows, int inner, int cols,
+            float* C, bool side = false) {
+  if (s->t_fresh)
+    return gemm_bf16(true, A, inner, true, WT, inner, C, cols, rows, cols, inner, 0, 0, side ? s->gw_side : s->gw,
+                     side ? s->gw_side_bytes : s->gw_bytes, side ? s->side : s->stream);
   return gemm_bf16(true, A, inner, false, W, cols, C, cols, rows, cols, inner, 0, 0, side ? s->gw_side : s->gw,
                    side ? s->gw_side_bytes : s->gw_bytes, side ? s->side : s->stream);
 }
@@ -697,8 +723,8 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
       break;
     }
     int rc = fork_side(s, st);
-    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], B, li, lo, s->U[j], true);
-    if (rc == DLM_OK) rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], (int)N, li, lo, s->Z[j]);
+    if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], s->PbT + s->oGT[j], B, li, lo, s->U[j], true);
+    if (rc == DLM_OK) rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], s->PbT + s->oLT[j], (int)N, li, lo, s->Z[j]);
     if (rc == DLM_OK) rc = join_side(s, st);
     if (rc != DLM_OK) return rc;
     const float* mean = s->run + s->orm[j];
@@ -760,6 +786,19 @@ int inv_backward(dlm_invnet* s, const float* targets, int B, float* loss, hipStr
   return DLM_OK;
 }
 
+// Lambda^T and Gamma^T of the hidden layers from their BF16 copies
+int inv_refresh_transposed(dlm_invnet* s, hipStream_t st) {
+  for (int j = 0; j + 1 < s->nl; ++j) {
+    const int li = s->lin[j], lo = s->lout[j];
+    const dim3 grid((unsigned)((lo + 63) / 64), (unsigned)((li + 63) / 64));
+    hipLaunchKernelGGL(inv_transpose_kernel, grid, dim3(256), 0, st, s->Pb + s->oLb[j], li, lo, s->PbT + s->oLT[j]);
+    hipLaunchKernelGGL(inv_transpose_kernel, grid, dim3(256), 0, st, s->Pb + s->oGb[j], li, lo, s->PbT + s->oGT[j]);
+  }
+  DLM_HIP(hipGetLastError());
+  s->t_fresh = true;
+  return DLM_OK;
+}
+
 int inv_refresh_bf16(dlm_invnet* s, hipStream_t st) {
   for (int j = 0; j < s->nl; ++j) {
     const int64_t c = (int64_t)s->lin[j] * s->lout[j];
@@ -767,7 +806,7 @@ int inv_refresh_bf16(dlm_invnet* s, hipStream_t st) {
     hipLaunchKernelGGL(inv_to_bf16_kernel, dim3(blocks(c)), dim3(256), 0, st, s->P + s->oG[j], s->Pb + s->oGb[j], c);
   }
   DLM_HIP(hipGetLastError());
-  return DLM_OK;
+  return inv_refresh_transposed(s, st);
 }
 
 int set_stream(dlm_invnet* s, hipStream_t st) {
@@ -865,6 +904,15 @@ int dlm_invnet_create(int32_t n, int32_t k, int32_t nl, const int32_t* widths, c
   parts.push_back({(void**)&s->Gr, 4 * o});
   parts.push_back({(void**)&s->run, 4 * std::max<int64_t>(orun, 1)});
   parts.push_back({(void**)&s->Pb, 2 * ob16});
+  int64_t obt = 0;
+  for (int j = 0; j < nl; ++j) {
+    const int64_t c = (int64_t)s->lin[j] * s->lout[j];
+    s->oLT.push_back(obt);
+    obt += (c + 7) & ~7ll;
+    s->oGT.push_back(obt);
+    obt += (c + 7) & ~7ll;
+  }
+  parts.push_back({(void**)&s->PbT, 2 * std::max<int64_t>(obt, 8)});
   s->X.assign(nl, nullptr);
   s->R.assign(nl, nullptr);
   s->Z.assign(nl, nullptr);
@@ -1003,8 +1051,10 @@ int dlm_invnet_train(dlm_invnet* s, const int16_t* colors, const float* targets,
       hipLaunchKernelGGL(inv_adam_kernel, dim3(blocks((s->total + 3) / 4)), dim3(256), 0, st, s->P, s->M, s->V,
                          s->Gr, s->total, lr, bc1, bc2, s->Pb, s->layout);
       DLM_HIP(hipGetLastError());
+      s->t_fresh = false;  // the next training forward reads Lambda itself
       ++step;
     }
+  if (rc == DLM_OK && !s->t_fresh) rc = inv_refresh_transposed(s, st);
   return rc;
 }
 

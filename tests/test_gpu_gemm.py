@@ -98,6 +98,20 @@ def test_exact_small_and_exact_fit(dlm, dev, ak, bk, shape):
         assert np.array_equal(got, A @ B), tile
 
 
+@pytest.mark.parametrize("shape", [(300, 292, 104), (256, 256, 64), (520, 264, 200), (130, 300, 72), (64, 70, 1000)])
+def test_exact_direct_to_lds(dlm, dev, shape):
+    """Both operands K-contiguous with pitches of 8 values: the kernel that
+    reads global memory straight into swizzled LDS, with windowed edge tiles,
+    a window that overlaps summed k (K not a multiple of 64), and splits."""
+    m, n, k = shape
+    say(f"gemm exact ints direct {m}x{n}x{k}")
+    da, db, A, B, sa, sb = operands(m, n, k, True, True, 0, 0, 700 + m + k, True)
+    for tile in (64, 128, 256):
+        for splits in (0, 1, 3):
+            got = run(dlm, da, db, m, n, k, True, True, sa, sb, tile=tile, splits=splits)
+            assert np.array_equal(got, A @ B), (tile, splits)
+
+
 @pytest.mark.parametrize("ak,bk", LAYOUTS)
 @pytest.mark.parametrize("splits", [2, 3, 5])
 def test_exact_split_k(dlm, dev, ak, bk, splits):
@@ -158,7 +172,7 @@ def test_empty_and_repeat(dlm, dev):
         dlm.gemm_bf16(da, db, m, n, k, True, False, tile=96)
 
 
-@pytest.mark.parametrize("form", ["rows", "at", "at-split", "wt"])
+@pytest.mark.parametrize("form", ["rows", "rows-t", "at", "at-split", "wt"])
 def test_network_shapes_sampled(dlm, dev, form):
     """The largest products of the paper-depth network for G(500, 0.5), k = 49:
     scoring chunks of 2048 colourings (100,352 class rows, 500 -> 5000) and
@@ -173,6 +187,15 @@ def test_network_shapes_sampled(dlm, dev, form):
         out = dlm.gemm_bf16(X.cuda(), W.cuda(), M, N, K, True, False)
         rows = np.random.default_rng(1).choice(M, 48, replace=False)
         A, B = X[rows].double().numpy(), W.double().numpy()
+        got = out[torch.from_numpy(rows).cuda()].cpu().double().numpy()
+    elif form == "rows-t":  # Z = X Lambda from Lambda^T at the 5000 -> 2500 layer (direct to LDS)
+        M, K, N = 4900, 5000, 2500
+        X = torch.randn(M, K, generator=g).to(torch.bfloat16)
+        WT = torch.randn(N, K, generator=g).to(torch.bfloat16)
+        say("gemm network rows from the transposed weight 4900 x 2500 x 5000")
+        out = dlm.gemm_bf16(X.cuda(), WT.cuda(), M, N, K, True, True)
+        rows = np.random.default_rng(5).choice(M, 48, replace=False)
+        A, B = X[rows].double().numpy(), WT.double().numpy().T
         got = out[torch.from_numpy(rows).cuda()].cpu().double().numpy()
     elif form == "at":  # dLambda = X^T dZ: X [4900][5000], dZ [4900][2500]
         R, M, N = 4900, 5000, 2500
