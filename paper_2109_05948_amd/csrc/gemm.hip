@@ -261,11 +261,130 @@ __device__ __forceinline__ void interleave() {
   }
 }
 
-template <int TM, bool AK, bool BK, int VEC, bool WIN>
+// Store a workgroup's tile: tile (i, j) value r of lane l is row
+// 32 i + 8 (r / 4) + 4 (l / 32) + r % 4, column 32 j + l % 32 of the wave's
+// quarter; rows below m0 and columns below n0 (a windowed edge tile's
+// overlap with its neighbour) and past M, N are not stored.  EV: the
+// evaluation epilogue (GemmEval) writes BF16 activations instead of C.
+template <int TM, bool EV>
+__device__ __forceinline__ void store_tile(const f16v (&acc)[TM][TM], int mr, int m0, int nr, int n0, int wm, int wn,
+                                           int lane, int M, int N, float* __restrict__ C, int64_t ldc,
+                                           const GemmEval& ev) {
+  const int lr = lane & 31, l4 = 4 * (lane >> 5);
+  constexpr int T = 64 * TM;
+  // an interior tile (the usual case) stores every value: no per-value tests
+  const bool interior = m0 == mr && n0 == nr && mr + T <= M && nr + T <= N;
+  if (!EV && interior) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) {
+        float* c = C + (int64_t)(mr + wm + 32 * i + l4) * ldc + (nr + wn + 32 * j + lr);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[(int64_t)(8 * (r >> 2) + (r & 3)) * ldc] = acc[i][j][r];
+      }
+    return;
+  }
+  if (!EV) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) {
+        const int n = nr + wn + 32 * j + lr;
+        if (n < N && n >= n0) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int m = mr + wm + 32 * i + 8 * (r >> 2) + l4 + (r & 3);
+            if (m < M && m >= m0) C[(int64_t)m * ldc + n] = acc[i][j][r];
+          }
+        }
+      }
+    return;
+  }
+  // evaluation epilogue: row m belongs to colouring m / k; a 32-row group
+  // starting at mi spans colouring c0 = mi / k and (k >= 32, checked on the
+  // host) at most c0 + 1.  Every parameter and U value the tile needs is
+  // read first (addresses clamped inside the arrays; values for columns or
+  // rows that are not stored go unused), so that the stores wait on nothing.
+  const int k = ev.k, cmax = (M - 1) / k;
+  float bb[TM], mm[TM], rs[TM], g[TM], sf[TM], u0[TM][TM], u1[TM][TM];
+  int c0[TM], r0[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int mi = mr + wm + 32 * i;
+    c0[i] = mi / k;
+    r0[i] = mi - c0[i] * k;
+  }
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    const int n = min(nr + wn + 32 * j + lr, N - 1);
+    bb[j] = ev.beta[n];
+    mm[j] = ev.mean[n];
+    rs[j] = ev.var[n];
+    g[j] = ev.gamma[n];
+    sf[j] = ev.mu[n];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      u0[i][j] = ev.u[(int64_t)min(c0[i], cmax) * N + n];
+      u1[i][j] = ev.u[(int64_t)min(c0[i] + 1, cmax) * N + n];
+    }
+  }
+  // y = ((acc + u + beta) - mean) * rs * gamma + mu = acc * sc + off, with
+  // sc per column and off per (colouring, column): one FMA per value, then
+  // LReLU and the hardware BF16 conversion (round to nearest even)
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    const float sc = g[j] / sqrtf(rs[j] + ev.eps);
+    g[j] = sc;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      u0[i][j] = ((u0[i][j] + bb[j]) - mm[j]) * sc + sf[j];
+      u1[i][j] = ((u1[i][j] + bb[j]) - mm[j]) * sc + sf[j];
+    }
+  }
+  if (interior) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TM; ++j) {
+        uint16_t* x = ev.x + (int64_t)(mr + wm + 32 * i + l4) * N + (nr + wn + 32 * j + lr);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int d = 8 * (r >> 2) + l4 + (r & 3);
+          const float yy = fmaf(acc[i][j][r], g[j], r0[i] + d >= k ? u1[i][j] : u0[i][j]);
+          const __bf16 o = (__bf16)(yy > 0.f ? yy : ev.slope * yy);
+          x[(int64_t)(8 * (r >> 2) + (r & 3)) * N] = __builtin_bit_cast(uint16_t, o);
+        }
+      }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int mi = mr + wm + 32 * i;
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      const int n = nr + wn + 32 * j + lr;
+      if (n < N && n >= n0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int d = 8 * (r >> 2) + l4 + (r & 3), m = mi + d;
+          if (m < M && m >= m0) {
+            const float yy = fmaf(acc[i][j][r], g[j], r0[i] + d >= k ? u1[i][j] : u0[i][j]);
+            const __bf16 o = (__bf16)(yy > 0.f ? yy : ev.slope * yy);
+            ev.x[(int64_t)m * N + n] = __builtin_bit_cast(uint16_t, o);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int TM, bool AK, bool BK, int VEC, bool WIN, bool EV>
 __global__ __launch_bounds__(THREADS) void gemm_bf16_kernel(const uint16_t* __restrict__ A, int64_t sa,
                                                             const uint16_t* __restrict__ B, int64_t sb,
                                                             float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                            int tiles_n, int kchunk, float* __restrict__ W) {
+                                                            int tiles_n, int kchunk, float* __restrict__ W,
+                                                            GemmEval ev) {
   constexpr int T = 64 * TM;
   __shared__ __align__(16) uint16_t sA[2][T * PITCH];
   __shared__ __align__(16) uint16_t sB[2][T * PITCH];
@@ -355,19 +474,7 @@ __global__ __launch_bounds__(THREADS) void gemm_bf16_kernel(const uint16_t* __re
 #undef DLM_GEMM_ISSUE
 #undef DLM_GEMM_PUT
 #undef DLM_GEMM_FIX
-  // tile (i, j): value r of lane l is C[32 i + 8 (r / 4) + 4 (l / 32) + r % 4][32 j + l % 32]
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TM; ++j) {
-      const int n = nr + wn + 32 * j + lr;
-      if (n >= N || n < n0) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = mr + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m < M && m >= m0) C[(int64_t)m * ldc + n] = acc[i][j][r];
-      }
-    }
+  store_tile<TM, EV>(acc, mr, m0, nr, n0, wm, wn, lane, M, N, C, ldc, ev);
 }
 
 // 16 bytes per lane from global memory straight into LDS (lane l writes LDS
@@ -455,11 +562,12 @@ __device__ __forceinline__ void mma_direct(const uint16_t* sA, const uint16_t* s
 // step's window overlaps k already summed, those chunks are zeroed in LDS
 // before the barrier.  An odd step count runs one step past the end, which
 // is all zeros.
-template <int TM>
+template <int TM, bool EV>
 __global__ __launch_bounds__(THREADS) void gemm_direct_kernel(const uint16_t* __restrict__ A, int64_t sa,
                                                               const uint16_t* __restrict__ B, int64_t sb,
                                                               float* __restrict__ C, int64_t ldc, int M, int N, int K,
-                                                              int tiles_n, int kchunk, float* __restrict__ W) {
+                                                              int tiles_n, int kchunk, float* __restrict__ W,
+                                                              GemmEval ev) {
   constexpr int T = 64 * TM;
   __shared__ __align__(16) uint16_t sA0[T * BKT];
   __shared__ __align__(16) uint16_t sA1[T * BKT];
@@ -552,19 +660,7 @@ __global__ __launch_bounds__(THREADS) void gemm_direct_kernel(const uint16_t* __
     for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1][i], fb[1][j], acc[i][j], 0, 0, 0);
 #undef DLM_DIRECT_ISSUE
 #undef DLM_DIRECT_MASK
-  // tile (i, j): value r of lane l is C[32 i + 8 (r / 4) + 4 (l / 32) + r % 4][32 j + l % 32]
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TM; ++j) {
-      const int n = nr + wn + 32 * j + lr;
-      if (n < n0) continue;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = mr + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m >= m0) C[(int64_t)m * ldc + n] = acc[i][j][r];
-      }
-    }
+  store_tile<TM, EV>(acc, mr, m0, nr, n0, wm, wn, lane, M, N, C, ldc, ev);
 }
 
 // C[m][n] = sum over s = 0 .. S-1 (in that order) of W[s][m][n]
@@ -589,31 +685,36 @@ int piece_width(const uint16_t* p, int64_t pitch, int64_t extent) {
 
 int64_t tiles(int64_t M, int64_t N, int t) { return ((M + t - 1) / t) * ((N + t - 1) / t); }
 
-template <int TM, int VEC, bool WIN>
+template <int TM, int VEC, bool WIN, bool EV>
 void launch_vec(bool ak, bool bk, dim3 grid, hipStream_t s, const uint16_t* A, int64_t sa, const uint16_t* B,
-                int64_t sb, float* C, int64_t ldc, int M, int N, int K, int tn, int kchunk, float* W) {
-  if (ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<TM, true, false, VEC, WIN>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc,
-                       M, N, K, tn, kchunk, W);
+                int64_t sb, float* C, int64_t ldc, int M, int N, int K, int tn, int kchunk, float* W,
+                const GemmEval& ev) {
+  if (EV || (ak && bk))  // the evaluation epilogue comes with K-contiguous operands only
+    hipLaunchKernelGGL((gemm_bf16_kernel<TM, true, true, VEC, WIN, EV>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C,
+                       ldc, M, N, K, tn, kchunk, W, ev);
+  else if (ak && !bk)
+    hipLaunchKernelGGL((gemm_bf16_kernel<TM, true, false, VEC, WIN, false>), grid, dim3(THREADS), 0, s, A, sa, B, sb,
+                       C, ldc, M, N, K, tn, kchunk, W, ev);
   else if (!ak && !bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<TM, false, false, VEC, WIN>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C,
-                       ldc, M, N, K, tn, kchunk, W);
-  else if (ak && bk)
-    hipLaunchKernelGGL((gemm_bf16_kernel<TM, true, true, VEC, WIN>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc,
-                       M, N, K, tn, kchunk, W);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TM, false, false, VEC, WIN, false>), grid, dim3(THREADS), 0, s, A, sa, B, sb,
+                       C, ldc, M, N, K, tn, kchunk, W, ev);
   else
-    hipLaunchKernelGGL((gemm_bf16_kernel<TM, false, true, VEC, WIN>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C,
-                       ldc, M, N, K, tn, kchunk, W);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TM, false, true, VEC, WIN, false>), grid, dim3(THREADS), 0, s, A, sa, B, sb,
+                       C, ldc, M, N, K, tn, kchunk, W, ev);
 }
 
+template <bool EV>
 void launch_direct(int tile, dim3 grid, hipStream_t s, const uint16_t* A, int64_t sa, const uint16_t* B, int64_t sb,
-                   float* C, int64_t ldc, int M, int N, int K, int tn, int kchunk, float* W) {
+                   float* C, int64_t ldc, int M, int N, int K, int tn, int kchunk, float* W, const GemmEval& ev) {
   if (tile == 256)
-    hipLaunchKernelGGL((gemm_direct_kernel<4>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+    hipLaunchKernelGGL((gemm_direct_kernel<4, EV>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn,
+                       kchunk, W, ev);
   else if (tile == 128)
-    hipLaunchKernelGGL((gemm_direct_kernel<2>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+    hipLaunchKernelGGL((gemm_direct_kernel<2, EV>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn,
+                       kchunk, W, ev);
   else
-    hipLaunchKernelGGL((gemm_direct_kernel<1>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+    hipLaunchKernelGGL((gemm_direct_kernel<1, EV>), grid, dim3(THREADS), 0, s, A, sa, B, sb, C, ldc, M, N, K, tn,
+                       kchunk, W, ev);
 }
 
 // the windowed kernels need 2- or 4-value pieces, a whole tile of rows in
@@ -668,19 +769,23 @@ GemmPlan gemm_plan(int M, int N, int K, int vec, int64_t ws_bytes, int tile, int
 // Host launch: C[M][N] (pitch ldc) = A(m, k) B(k, n) as described above.
 // tile / splits: 0 chooses from the shape, else forced (a split needs
 // splits M N 4 bytes of workspace; a tile the shape cannot take falls back
-// to 64).
+// to 64).  eval: write the evaluation epilogue's BF16 activations instead
+// of C (both operands K-contiguous, no split; C unused).
 int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, const uint16_t* B, int64_t sb, float* C,
-              int64_t ldc, int M, int N, int K, int tile, int splits, void* ws, int64_t ws_bytes, hipStream_t s) {
+              int64_t ldc, int M, int N, int K, int tile, int splits, void* ws, int64_t ws_bytes, hipStream_t s,
+              const GemmEval* eval) {
   if (M < 0 || N < 0 || K < 0 || ldc < N || splits < 0 || splits > 64 || ws_bytes < 0)
     return set_error(DLM_E_INVAL, "gemm_bf16: M=%d N=%d K=%d ldc=%lld splits=%d", M, N, K, (long long)ldc, splits);
   if (tile != 0 && tile != 64 && tile != 128 && tile != 256)
     return set_error(DLM_E_INVAL, "gemm_bf16: tile %d (need 0, 64, 128 or 256)", tile);
   if (M == 0 || N == 0) return DLM_OK;
-  if (!A || !B || !C) return set_error(DLM_E_INVAL, "gemm_bf16: null operand");
+  if (!A || !B || (!C && !eval)) return set_error(DLM_E_INVAL, "gemm_bf16: null operand");
   if ((a_kcontig ? sa < K : sa < M) || (b_kcontig ? sb < K : sb < N))
     return set_error(DLM_E_INVAL, "gemm_bf16: pitch smaller than the contiguous extent");
   if (sa > (1 << 22) || sb > (1 << 22))  // lane offsets within one step stay below 2^31 values
     return set_error(DLM_E_INVAL, "gemm_bf16: pitch above 2^22 values");
+  if (eval && (!a_kcontig || !b_kcontig || splits > 1 || eval->k < 32 || !eval->x || !eval->u))
+    return set_error(DLM_E_INVAL, "gemm_bf16: the evaluation epilogue needs K-contiguous operands, no split, k >= 32");
   if (splits > 1 && (!ws || (int64_t)splits * M * N * 4 > ws_bytes))
     return set_error(DLM_E_INVAL, "gemm_bf16: %d splits need %lld bytes of workspace", splits,
                      (long long)splits * M * N * 4);
@@ -688,7 +793,7 @@ int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, con
   const int va = gemm::piece_width(A, sa, a_kcontig ? K : M), vb = gemm::piece_width(B, sb, b_kcontig ? K : N);
   const int vec = va < vb ? va : vb;
   if (tile > 64 && !gemm::windowed(M, N, K, vec, tile)) tile = 64;
-  const GemmPlan p = gemm_plan(M, N, K, vec, ws ? ws_bytes : 0, tile, splits);
+  const GemmPlan p = gemm_plan(M, N, K, vec, (ws && !eval) ? ws_bytes : 0, tile, eval ? 1 : splits);
   const int S = p.splits;
   const int steps = (K + gemm::BKT - 1) / gemm::BKT;
   const int kchunk = S > 1 ? ((steps + S - 1) / S) * gemm::BKT : std::max(K, 1);
@@ -698,39 +803,50 @@ int gemm_bf16(bool a_kcontig, const uint16_t* A, int64_t sa, bool b_kcontig, con
   if (nt > 0x7fffffff) return set_error(DLM_E_INVAL, "gemm_bf16: %lld tiles", (long long)nt);
   const dim3 grid((unsigned)nt, (unsigned)Sg);
   float* W = (float*)ws;
+  const GemmEval ev = eval ? *eval : GemmEval{};
   const bool win = gemm::windowed(M, N, K, vec, p.tile);
   // both operands K-contiguous with 16-byte aligned rows and K steps: the
   // direct-to-LDS kernel
   const bool direct = win && a_kcontig && b_kcontig && K % 8 == 0 && sa % 8 == 0 && sb % 8 == 0 &&
                       reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
   if (direct) {
-    gemm::launch_direct(p.tile, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W);
+    if (eval)
+      gemm::launch_direct<true>(p.tile, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W, ev);
+    else
+      gemm::launch_direct<false>(p.tile, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W, ev);
   } else {
-#define DLM_GEMM_LAUNCH(TM, V, WIN) \
-  gemm::launch_vec<TM, V, WIN>(a_kcontig, b_kcontig, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, W)
-  if (p.tile == 256) {
-    if (vec == 4)
-      DLM_GEMM_LAUNCH(4, 4, true);
-    else
-      DLM_GEMM_LAUNCH(4, 2, true);
-  } else if (p.tile == 128) {
-    if (vec == 4)
-      DLM_GEMM_LAUNCH(2, 4, true);
-    else
-      DLM_GEMM_LAUNCH(2, 2, true);
-  } else if (win) {
-    if (vec == 4)
-      DLM_GEMM_LAUNCH(1, 4, true);
-    else
-      DLM_GEMM_LAUNCH(1, 2, true);
-  } else {
-    if (vec == 4)
-      DLM_GEMM_LAUNCH(1, 4, false);
-    else if (vec == 2)
-      DLM_GEMM_LAUNCH(1, 2, false);
-    else
-      DLM_GEMM_LAUNCH(1, 1, false);
-  }
+#define DLM_GEMM_LAUNCH(TM, V, WIN)                                                                              \
+  do {                                                                                                           \
+    if (eval)                                                                                                    \
+      gemm::launch_vec<TM, V, WIN, true>(a_kcontig, b_kcontig, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn, kchunk, \
+                                         W, ev);                                                                 \
+    else                                                                                                         \
+      gemm::launch_vec<TM, V, WIN, false>(a_kcontig, b_kcontig, grid, s, A, sa, B, sb, C, ldc, M, N, K, tn,     \
+                                          kchunk, W, ev);                                                        \
+  } while (0)
+    if (p.tile == 256) {
+      if (vec == 4)
+        DLM_GEMM_LAUNCH(4, 4, true);
+      else
+        DLM_GEMM_LAUNCH(4, 2, true);
+    } else if (p.tile == 128) {
+      if (vec == 4)
+        DLM_GEMM_LAUNCH(2, 4, true);
+      else
+        DLM_GEMM_LAUNCH(2, 2, true);
+    } else if (win) {
+      if (vec == 4)
+        DLM_GEMM_LAUNCH(1, 4, true);
+      else
+        DLM_GEMM_LAUNCH(1, 2, true);
+    } else {
+      if (vec == 4)
+        DLM_GEMM_LAUNCH(1, 4, false);
+      else if (vec == 2)
+        DLM_GEMM_LAUNCH(1, 2, false);
+      else
+        DLM_GEMM_LAUNCH(1, 1, false);
+    }
 #undef DLM_GEMM_LAUNCH
   }
   DLM_HIP(hipGetLastError());

@@ -722,6 +722,22 @@ int inv_forward(dlm_invnet* s, const int16_t* colors, int B, bool train, bool up
                          s->P + s->oG[j], s->P + s->ob[j], k, li, s->fout);
       break;
     }
+    if (!train && s->t_fresh && k >= 32) {
+      // evaluation: U = R Gamma first, then X Lambda with the layer's bias,
+      // normalisation (running estimates), scale, shift and LReLU applied
+      // as its results are stored (BF16 X of the next layer, no FP32 Z),
+      // then the class means of the new activations
+      int rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], s->PbT + s->oGT[j], B, li, lo, s->U[j]);
+      const GemmEval ev{s->U[j], s->P + s->ob[j], s->run + s->orm[j], s->run + s->orv[j], s->P + s->og[j],
+                        s->P + s->om[j], k, kInvSlope, kBnEps, s->X[j + 1]};
+      if (rc == DLM_OK)
+        rc = gemm_bf16(true, s->X[j], li, true, s->PbT + s->oLT[j], li, nullptr, lo, (int)N, lo, li, 0, 0, nullptr, 0,
+                       st, &ev);
+      if (rc != DLM_OK) return rc;
+      hipLaunchKernelGGL(inv_class_mean_kernel, dim3((unsigned)((lo + 255) / 256), (unsigned)B), dim3(256), 0, st,
+                         s->X[j + 1], k, lo, s->R[j + 1]);
+      continue;
+    }
     int rc = fork_side(s, st);
     if (rc == DLM_OK) rc = mm_rows(s, s->R[j], s->Pb + s->oGb[j], s->PbT + s->oGT[j], B, li, lo, s->U[j], true);
     if (rc == DLM_OK) rc = mm_rows(s, s->X[j], s->Pb + s->oLb[j], s->PbT + s->oLT[j], (int)N, li, lo, s->Z[j]);

@@ -77,7 +77,13 @@ def f32(P):
 SMALL = [(40, 5, [48, 33, 1], 9), (130, 7, [200, 70, 70, 1], 24), (65, 3, [5, 1], 2)]
 
 
-@pytest.mark.parametrize("n,k,widths,b", SMALL)
+# k >= 32: evaluation takes the fused product (bias, normalisation, LReLU and
+# the BF16 store applied to the accumulators); widths 136 / 264 take the
+# direct-to-LDS kernel (pitches of 8 values), 70 the register one
+FUSED = [(72, 33, [136, 70, 1], 12), (96, 40, [264, 136, 1], 9), (50, 35, [70, 1], 5)]
+
+
+@pytest.mark.parametrize("n,k,widths,b", SMALL + FUSED)
 def test_forward_eval(dlm, dev, n, k, widths, b):
     rng = np.random.default_rng(1)
     colors = rng.integers(0, k, size=(b, n)).astype(np.int16)
