@@ -42,7 +42,7 @@
 // W[s][M][N] and a second kernel sums the S partials in order s = 0 .. S-1.
 // Results therefore depend only on (M, N, K, tile, S): repeated calls agree
 // bit for bit.
-#include "dlm_common.h"
+#include "gemm.h"
 
 namespace dlm {
 

@@ -15,7 +15,7 @@
 // Adam are the kernels below.  All reductions run in a fixed order.
 #include <vector>
 
-#include "dlm_common.h"
+#include "gemm.h"
 
 namespace dlm {
 
