@@ -382,6 +382,15 @@ int dlm_gather_rows(const int16_t* src_dev, int32_t rows, int32_t n, const int32
  * training targets for one generation. */
 int dlm_standardize(const int32_t* f_dev, int32_t count, float* out_dev, void* stream);
 
+/* Training scores of one WVCP generation (Section 2.3 trains on the
+ * post-search score; a search that met no legal colouring, score
+ * 0x7fffffff, takes the worst legal score of the generation):
+ * out_dev[i] = f_dev[i] if legal, else max over the legal f_dev; the
+ * device int *any_legal_dev is set to 1 if some f_dev[i] is legal, else 0
+ * (out_dev is then a copy of f_dev and the generation trains nothing).
+ * count >= 1; out_dev may equal f_dev.  Asynchronous on stream. */
+int dlm_wvcp_targets(const int32_t* f_dev, int32_t count, int32_t* out_dev, int32_t* any_legal_dev, void* stream);
+
 /* pairs_dev int32[pop][2] = (i, j): j uniform over the other members,
  * j = floor(w0 (pop - 1) / 2^32) + (that value >= i), w0 = word 0 of
  * Philox(seed; i, gen, 0, 0x80000009). */

@@ -133,3 +133,19 @@ def train(P: dict, colors: np.ndarray, targets: np.ndarray, k: int, batch: int, 
             opt.step(P, G)
             losses.append(loss)
     return P, opt, losses
+
+
+NO_LEGAL = 0x7FFFFFFF  # a WVCP search that met no legal colouring
+
+
+def wvcp_targets(f: np.ndarray):
+    """Training scores of one WVCP generation (Section 2.3 trains the scorer
+    on the post-search score f(S'); a search that met no legal colouring has
+    none, and takes the worst legal score of its generation).  Returns None
+    when no search of the generation met a legal colouring (no training)."""
+    f = np.asarray(f, dtype=np.int64)
+    legal = [v for v in f if v != NO_LEGAL]
+    if not legal:
+        return None
+    worst = max(legal)
+    return np.array([v if v != NO_LEGAL else worst for v in f], dtype=np.int64)

@@ -15,6 +15,7 @@ from ._abi import (  # noqa: F401
     evaluate,
     gather_distances,
     gemm_bf16,
+    wvcp_targets,
     gather_pool,
     gather_rows,
     nearest,

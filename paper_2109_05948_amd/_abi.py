@@ -37,7 +37,7 @@ EXPORTS = [
     "dlm_partition_distance", "dlm_spacing_update", "dlm_gather_distances", "dlm_gather_pool",
     "dlm_nearest", "dlm_select_groups", "dlm_reduce_colours", "dlm_invnet_create",
     "dlm_invnet_destroy", "dlm_invnet_num_params", "dlm_invnet_get_params", "dlm_invnet_forward",
-    "dlm_invnet_grad", "dlm_invnet_train", "dlm_gemm_bf16",
+    "dlm_invnet_grad", "dlm_invnet_train", "dlm_gemm_bf16", "dlm_wvcp_targets",
 ]
 
 
@@ -108,6 +108,7 @@ def lib():
             L.dlm_invnet_forward.argtypes = [P, P, I32, P, P]
             L.dlm_invnet_grad.argtypes = [P, P, P, I32, P, P, P]
             L.dlm_invnet_train.argtypes = [P, P, P, I32, I32, I32, C.c_float, P, P]
+            L.dlm_wvcp_targets.argtypes = [P, I32, P, P, P]
             L.dlm_gemm_bf16.argtypes = [I32, P, I64, I32, P, I64, P, I64, I32, I32, I32, I32, I32, P, I64, P]
             for name in EXPORTS:
                 getattr(L, name)
@@ -541,6 +542,16 @@ def standardize(f: torch.Tensor, out: torch.Tensor | None = None, stream=None):
     out = out if out is not None else torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
     _check("dlm_standardize", lib().dlm_standardize(_ptr(f), f.shape[0], _ptr(out), _stream(stream)))
     return out
+
+
+def wvcp_targets(f: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """dlm_wvcp_targets -> (targets int32 [count], device flag int32 [1]:
+    1 if some search met a legal colouring)."""
+    _dev(f, torch.int32, "f")
+    out = out if out is not None else torch.empty_like(f)
+    flag = torch.empty(1, dtype=torch.int32, device=f.device)
+    _check("dlm_wvcp_targets", lib().dlm_wvcp_targets(_ptr(f), f.numel(), _ptr(out), _ptr(flag), _stream(stream)))
+    return out, flag
 
 
 def random_pairs(pop: int, seed: int, gen: int, out: torch.Tensor | None = None, stream=None):

@@ -19,6 +19,27 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const int16_t* __restr
 }
 
 // mean and standard deviation in FP64, fixed order, one workgroup
+// out[i] = f[i], or the largest f below 0x7fffffff (the worst legal score)
+// where f[i] = 0x7fffffff (no legal colouring met); *any = 1 if some f[i]
+// is legal, else 0 (and out is left as f).  One workgroup.
+__global__ __launch_bounds__(256) void wvcp_targets_kernel(const int32_t* __restrict__ f, int32_t count,
+                                                           int32_t* __restrict__ out, int32_t* __restrict__ any) {
+  __shared__ int32_t red[256];
+  int32_t w = INT32_MIN;
+  for (int i = threadIdx.x; i < count; i += 256)
+    if (f[i] != 0x7fffffff) w = max(w, f[i]);
+  red[threadIdx.x] = w;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const int32_t worst = red[0];
+  const bool ok = worst != INT32_MIN;
+  for (int i = threadIdx.x; i < count; i += 256) out[i] = (ok && f[i] == 0x7fffffff) ? worst : f[i];
+  if (threadIdx.x == 0) any[0] = ok ? 1 : 0;
+}
+
 __global__ __launch_bounds__(256) void standardize_kernel(const int32_t* __restrict__ f, int32_t count,
                                                           float* __restrict__ out) {
   __shared__ double red[256];
@@ -186,6 +207,13 @@ int dlm_gather_rows(const int16_t* src, int32_t rows, int32_t n, const int32_t* 
 int dlm_standardize(const int32_t* f, int32_t count, float* out, void* stream) {
   if (count < 1 || !f || !out) return set_error(DLM_E_INVAL, "dlm_standardize: bad arguments");
   hipLaunchKernelGGL(standardize_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, f, count, out);
+  DLM_HIP(hipGetLastError());
+  return DLM_OK;
+}
+
+int dlm_wvcp_targets(const int32_t* f, int32_t count, int32_t* out, int32_t* any_legal, void* stream) {
+  if (count < 1 || !f || !out || !any_legal) return set_error(DLM_E_INVAL, "dlm_wvcp_targets: bad arguments");
+  hipLaunchKernelGGL(wvcp_targets_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, f, count, out, any_legal);
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }

@@ -74,13 +74,11 @@ def prediction_quality(pred: torch.Tensor, actual: torch.Tensor, mean: float, sd
 
 
 def wvcp_targets(f: torch.Tensor):
-    """Training scores of a WVCP generation: a search that met no legal
-    colouring (score 0x7fffffff) gets the generation's worst legal score;
-    None when no search met one."""
-    legal = f != 0x7FFFFFFF
-    if not bool(legal.any()):
-        return None
-    return torch.where(legal, f, f[legal].max())
+    """Training scores of a WVCP generation (dlm_wvcp_targets): a search that
+    met no legal colouring (score 0x7fffffff) gets the generation's worst
+    legal score; None when no search met one."""
+    t, any_legal = A.wvcp_targets(f)
+    return t if int(any_legal.item()) else None
 
 
 def _score_scale(f: torch.Tensor) -> tuple:

@@ -305,3 +305,24 @@ def test_weighted_diversity_generation_replay(dlm, dev):
     pick, _ = dv.spacing_update(fs, dv.distance_matrix(rows, rows, k), pop, g.n // 10)
     assert (res.f.cpu().numpy() == fs[pick]).all()
     assert (res.colors.cpu().numpy() == rows[pick]).all()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("count,frac,seed", [(1, 0.0, 1), (1, 1.0, 2), (37, 0.3, 3), (5000, 0.05, 4), (700, 1.0, 5),
+                                             (700, 0.0, 6)])
+def test_wvcp_targets_parity(dev, count, frac, seed):
+    """dlm_wvcp_targets against the oracle's rule: random legal scores with a
+    fraction frac of searches that met no legal colouring (all, none, one)."""
+    import paper_2109_05948_amd as dlm
+    from oracle.scorer import wvcp_targets
+    rng = np.random.default_rng(seed)
+    f = rng.integers(1, 1 << 30, size=count).astype(np.int32)
+    f[rng.random(count) < frac] = 0x7FFFFFFF
+    print(f"wvcp targets count={count} frac={frac}", flush=True)
+    got, flag = dlm.wvcp_targets(torch.from_numpy(f).cuda())
+    want = wvcp_targets(f)
+    if want is None:
+        assert int(flag.item()) == 0
+    else:
+        assert int(flag.item()) == 1
+        assert np.array_equal(got.cpu().numpy().astype(np.int64), want)

@@ -43,9 +43,11 @@ def test_degenerate_cases_give_nan():
     assert all(math.isnan(x) for x in prediction_quality(torch.zeros(1), actual[:1], 2.0, 1.0))
 
 
-def test_wvcp_targets():
-    from paper_2109_05948_amd.memetic import wvcp_targets
-    f = torch.tensor([120, 0x7FFFFFFF, 90, 0x7FFFFFFF], dtype=torch.int32)
-    assert wvcp_targets(f).tolist() == [120, 120, 90, 120]
-    assert wvcp_targets(torch.tensor([7, 5], dtype=torch.int32)).tolist() == [7, 5]
-    assert wvcp_targets(torch.full((3,), 0x7FFFFFFF, dtype=torch.int32)) is None
+def test_wvcp_targets_oracle():
+    """The oracle's training-target rule for WVCP generations, on hand cases:
+    the worst legal score replaces the searches without a legal colouring."""
+    from oracle.scorer import wvcp_targets
+    assert wvcp_targets([120, 0x7FFFFFFF, 90, 0x7FFFFFFF]).tolist() == [120, 120, 90, 120]
+    assert wvcp_targets([7, 5]).tolist() == [7, 5]
+    assert wvcp_targets([0x7FFFFFFF] * 3) is None
+    assert wvcp_targets([0x7FFFFFFE, 0x7FFFFFFF]).tolist() == [0x7FFFFFFE, 0x7FFFFFFE]
