@@ -171,6 +171,9 @@ def main():
                     help="popsweep: the weighted graph")
     ap.add_argument("--passes", type=int, default=3,
                     help="popsweep: budget = this many local-search passes of the largest population")
+    ap.add_argument("--budget-pop", type=int, default=0,
+                    help="popsweep: the population the budget's passes are counted in (default: the largest of "
+                         "--pops), so that runs split over several commands share one budget")
     ap.add_argument("--cutoff", type=float, default=300.0,
                     help="memetic1000: wall-clock limit per loop (seconds)")
     ap.add_argument("--loops", default="plain,learned", help="memetic1000: which loops to run")
@@ -551,7 +554,7 @@ def bench_popsweep(args, w, wm, dlm, torch):
     pops = [int(x) for x in args.pops.split(",")]
     seeds = [int(x) for x in args.seeds.split(",")]
     per_search = 10 * g.n * 10
-    budget = args.passes * max(pops) * per_search
+    budget = args.passes * (args.budget_pop or max(pops)) * per_search
     e = wm.extra
     out_runs = []
     for p in pops:
@@ -563,7 +566,8 @@ def bench_popsweep(args, w, wm, dlm, torch):
                             children_per_pair=e["children_per_pair"], keep_frac=e["keep_frac"],
                             scorer_params=scorer_weights(g.n, seed=0), batch=min(e["batch"], p),
                             epochs=e["epochs"], lr=e["lr"], weighted=True, rounds=10, log=log,
-                            diversity=args.diversity > 0, neighbours=max(args.diversity, 1))
+                            diversity=args.diversity > 0, neighbours=max(args.diversity, 1),
+                            slice_rows=8192)
             out_runs.append({"population": p, "seed": sd, "generations": r.generations,
                              "best_wscore": r.best, "wall_s": r.wall, "moves": r.tabu_moves,
                              "history": [[h[0], h[1], h[2]] for h in r.history]})

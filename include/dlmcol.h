@@ -464,8 +464,11 @@ int dlm_partition_distance(int32_t n, int32_t k, const int16_t* a_dev, int32_t n
  *   pick_dev      int32 [keep] output: pool indices in the order taken
  *   n_spaced_dev  int32 [1] output: how many were taken under the spacing
  *   workspace_dev caller-owned scratch of 4 (na + nb) bytes
- * na + nb <= 65536, 0 <= keep <= na + nb, ld >= na + nb.  One workgroup
- * walks the pool (one barrier per member examined). */
+ * na + nb <= 65536, 0 <= keep <= na + nb, ld >= na + nb.  The walk goes in
+ * chunks of 512 members: many workgroups check a chunk against the members
+ * taken before it, then one workgroup settles the chunk in order; the result
+ * is that of the one-at-a-time walk.  n_spaced_dev also carries the running
+ * count between the chunks, so it must not alias another argument. */
 int dlm_spacing_update(const int32_t* fa_dev, int32_t na, const int32_t* fb_dev, int32_t nb,
                        const int32_t* dist_dev, int64_t ld, int32_t keep, int32_t spacing,
                        int32_t* pick_dev, int32_t* n_spaced_dev, void* workspace_dev, void* stream);

@@ -262,38 +262,138 @@ __global__ __launch_bounds__(256) void pool_rank_kernel(const int32_t* __restric
 
 constexpr int kMaxPool = 1 << 16;
 
-__global__ __launch_bounds__(1024) void spacing_kernel(const int32_t* __restrict__ order, int32_t total, int32_t keep,
-                                                       const int32_t* __restrict__ dist, int64_t ld,
-                                                       int32_t spacing, int32_t* __restrict__ pick,
-                                                       int32_t* __restrict__ n_spaced) {
-  __shared__ uint32_t taken[kMaxPool / 32];
-  const int tid = threadIdx.x;
-  for (int w = tid; w < (total + 31) / 32; w += blockDim.x) taken[w] = 0u;
-  __syncthreads();
-  int count = 0;  // the same in every thread
-  for (int r = 0; r < total && count < keep; ++r) {
-    const int c = order[r];
-    int ok = 1;
-    for (int s = tid; s < count; s += blockDim.x) {
-      const int o = pick[s];
-      const int lo = c < o ? c : o, hi = c < o ? o : c;
-      ok &= dist[(size_t)lo * ld + hi] > spacing;  // the upper triangle holds the pool's distances
-    }
-    if (__syncthreads_and(ok)) {
-      if (tid == 0) {
-        pick[count] = c;
-        taken[c / 32] |= 1u << (c % 32);
-      }
-      ++count;
-      __syncthreads();  // pick[count - 1] is read by every thread from the next candidate on
-    }
+// The update under a minimum spacing goes through the quality order in
+// chunks of kChunk members.  Many workgroups screen a chunk's members
+// against the members taken in earlier chunks; then one workgroup settles
+// the chunk's survivors among themselves, in order, from a conflict bit
+// matrix in LDS.  A member joins exactly when it would in the one-at-a-time
+// walk: it is too close to no member taken before it.  order[r] keeps the
+// pool index in its low bits, kBlocked on a member too close to an earlier
+// chunk's member, kTaken on a member that joined.  n_spaced holds the running
+// count between the launches.
+constexpr int kChunk = 512;
+constexpr int32_t kIndexMask = 0x1ffff, kBlocked = 1 << 29, kTaken = 1 << 30;
+
+__device__ inline int32_t pool_dist(const int32_t* __restrict__ dist, int64_t ld, int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return dist[(size_t)lo * ld + hi];  // the upper triangle holds the pool's distances
+}
+
+// one workgroup per member r0 + blockIdx.x, against pick[0 .. count)
+__global__ __launch_bounds__(256) void spacing_screen_kernel(int32_t* __restrict__ order, int32_t r0,
+                                                             const int32_t* __restrict__ dist, int64_t ld,
+                                                             int32_t keep, int32_t spacing,
+                                                             const int32_t* __restrict__ pick,
+                                                             const int32_t* __restrict__ n_spaced) {
+  const int count = *n_spaced;
+  if (count >= keep) return;
+  const int r = r0 + blockIdx.x;
+  const int c = order[r] & kIndexMask;
+  int hit = 0;
+#pragma unroll 4
+  for (int s = threadIdx.x; s < count; s += blockDim.x) hit |= pool_dist(dist, ld, c, pick[s]) <= spacing;
+  if (__syncthreads_or(hit) && threadIdx.x == 0) order[r] = c | kBlocked;
+}
+
+// the chunk [r0, r0 + cnt): its unblocked members in order, each joining
+// unless too close to one of them that joined before it, until keep
+__global__ __launch_bounds__(1024) void spacing_resolve_kernel(int32_t* __restrict__ order, int32_t r0, int32_t cnt,
+                                                               const int32_t* __restrict__ dist, int64_t ld,
+                                                               int32_t keep, int32_t spacing, int32_t first,
+                                                               int32_t* __restrict__ pick,
+                                                               int32_t* __restrict__ n_spaced) {
+  __shared__ uint32_t conf[kChunk][kChunk / 32];  // row b, bit a < b: survivors a and b too close
+  __shared__ int32_t surv[kChunk];                // pool index of each survivor, in order
+  __shared__ int16_t spos[kChunk];                // its position in the chunk
+  __shared__ int32_t wave_total[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int count0 = first ? 0 : *n_spaced;
+  if (count0 >= keep) {
+    if (first && tid == 0) *n_spaced = 0;
+    return;
   }
-  if (tid == 0) {
-    *n_spaced = count;
-    for (int r = 0; r < total && count < keep; ++r) {
-      const int c = order[r];
-      if (!((taken[c / 32] >> (c % 32)) & 1u)) pick[count++] = c;
+  const int32_t v = tid < cnt ? order[r0 + tid] : kBlocked;
+  const bool alive = !(v & kBlocked);
+  const uint64_t m = __ballot(alive);
+  if (lane == 0) wave_total[wave] = __popcll(m);
+  __syncthreads();
+  int before = 0, S = 0;
+  for (int w = 0; w < 16; ++w) {
+    const int t = wave_total[w];
+    before += w < wave ? t : 0;
+    S += t;
+  }
+  if (alive) {
+    const int at = before + __popcll(m & ((1ull << lane) - 1ull));
+    surv[at] = v & kIndexMask;
+    spos[at] = (int16_t)tid;
+  }
+  __syncthreads();
+  const int W = (S + 31) / 32;
+  for (int task = tid; task < S * W; task += blockDim.x) {
+    const int b = task / W, w = task % W;
+    uint32_t word = 0u;
+    if (32 * w < b) {
+      // all 32 loads are issued before the first result is needed: a >= b
+      // reads the pair (surv[0], surv[b]) and is masked off
+      const int cb = surv[b];
+      int32_t d[32];
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const int a = 32 * w + j;
+        d[j] = pool_dist(dist, ld, surv[a < b ? a : 0], cb);
+      }
+#pragma unroll
+      for (int j = 0; j < 32; ++j) word |= (uint32_t)(32 * w + j < b && d[j] <= spacing) << j;
     }
+    conf[b][w] = word;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t acc = 0u;  // lane w < W: word w of the survivors that joined
+    int count = count0;
+    for (int b = 0; b < S && count < keep; ++b) {
+      const uint32_t row = lane < W ? conf[b][lane] : 0u;
+      if (__ballot((row & acc) != 0u) == 0ull) {
+        if (lane == (b >> 5)) acc |= 1u << (b & 31);
+        if (lane == 0) {
+          pick[count] = surv[b];
+          order[r0 + spos[b]] = surv[b] | kTaken;
+        }
+        ++count;
+      }
+    }
+    if (lane == 0) *n_spaced = count;
+  }
+}
+
+// places left after the spacing walk: the best members not taken, in order
+__global__ __launch_bounds__(1024) void spacing_fill_kernel(const int32_t* __restrict__ order, int32_t total,
+                                                            int32_t keep, int32_t first, int32_t* __restrict__ pick,
+                                                            int32_t* __restrict__ n_spaced) {
+  __shared__ int32_t wave_total[16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int count = first ? 0 : *n_spaced;
+  if (first && tid == 0) *n_spaced = 0;
+  for (int base = 0; base < total && count < keep; base += blockDim.x) {
+    const int r = base + tid;
+    const int32_t v = r < total ? order[r] : kTaken;
+    const bool want = !(v & kTaken);
+    const uint64_t m = __ballot(want);
+    if (lane == 0) wave_total[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int t = wave_total[w];
+      before += w < wave ? t : 0;
+      all += t;
+    }
+    if (want) {
+      const int at = count + before + __popcll(m & ((1ull << lane) - 1ull));
+      if (at < keep) pick[at] = v & kIndexMask;
+    }
+    count += all;
+    __syncthreads();  // wave_total is written again
   }
 }
 
@@ -421,17 +521,26 @@ int dlm_spacing_update(const int32_t* fa, int32_t na, const int32_t* fb, int32_t
   const int64_t total = (int64_t)na + nb;
   if (na < 0 || nb < 0 || total > kMaxPool || keep < 0 || keep > total || ld < total)
     return set_error(DLM_E_INVAL, "dlm_spacing_update: na=%d nb=%d keep=%d ld=%lld", na, nb, keep, (long long)ld);
-  if (!pick || !n_spaced || (total > 0 && (!dist || !workspace)) || (na > 0 && !fa) || (nb > 0 && !fb))
+  if ((keep > 0 && !pick) || !n_spaced || (total > 0 && (!dist || !workspace)) || (na > 0 && !fa) || (nb > 0 && !fb))
     return set_error(DLM_E_INVAL, "dlm_spacing_update: null buffer");
   hipStream_t s = (hipStream_t)stream;
   int32_t* order = (int32_t*)workspace;
-  if (total > 0) {
-    hipLaunchKernelGGL(pool_rank_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, fa, na, fb, nb,
-                       order);
+  if (total == 0) {
+    hipLaunchKernelGGL(spacing_fill_kernel, dim3(1), dim3(1024), 0, s, order, 0, keep, 1, pick, n_spaced);
     DLM_HIP(hipGetLastError());
+    return DLM_OK;
   }
-  hipLaunchKernelGGL(spacing_kernel, dim3(1), dim3(1024), 0, s, order, (int32_t)total, keep, dist, ld, spacing, pick,
-                     n_spaced);
+  hipLaunchKernelGGL(pool_rank_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, fa, na, fb, nb, order);
+  DLM_HIP(hipGetLastError());
+  for (int32_t r0 = 0; r0 < total; r0 += kChunk) {
+    const int32_t cnt = (int32_t)std::min<int64_t>(kChunk, total - r0);
+    if (r0 > 0)
+      hipLaunchKernelGGL(spacing_screen_kernel, dim3((unsigned)cnt), dim3(256), 0, s, order, r0, dist, ld, keep,
+                         spacing, pick, n_spaced);
+    hipLaunchKernelGGL(spacing_resolve_kernel, dim3(1), dim3(1024), 0, s, order, r0, cnt, dist, ld, keep, spacing,
+                       (int32_t)(r0 == 0), pick, n_spaced);
+  }
+  hipLaunchKernelGGL(spacing_fill_kernel, dim3(1), dim3(1024), 0, s, order, (int32_t)total, keep, 0, pick, n_spaced);
   DLM_HIP(hipGetLastError());
   return DLM_OK;
 }

@@ -93,7 +93,8 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         epochs: int = 5, lr: float = 1e-3, block: int = 0, table: str = "auto",
         log=None, diversity: bool = False, neighbours: int = 16,
         init_colors: torch.Tensor | None = None, weighted: bool = False, rounds: int = 10,
-        target: int | None = None, network: str = "mlp", eval_chunk: int = 1024) -> MemeticResult:
+        target: int | None = None, network: str = "mlp", eval_chunk: int = 1024,
+        slice_rows: int = 0) -> MemeticResult:
     """One loop of Algorithm 1.  With ``weighted`` it solves the WVCP
     (Section 2.2): the start is the greedy colouring (k = 0 takes the largest
     number of colours it uses), the local search is Algorithm 2 with
@@ -108,7 +109,11 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
     "invariant" is the paper's colour-invariant network of Section 2.3
     (dlm_invnet, ``scorer_params`` its weights with a "widths" entry),
     trained at ``batch`` colourings per step and evaluated in chunks of
-    ``eval_chunk``."""
+    ``eval_chunk``.
+
+    ``slice_rows`` > 0 runs each local-search pass in launches of at most
+    that many individuals, logging each; every individual keeps its own
+    random stream (``ind_base``), so the results do not change."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if target is None:
         target = -1 if weighted else 0
@@ -137,11 +142,23 @@ def run(graph: A.Graph, k: int, pop: int, iters: int, learned: bool, seed: int =
         cols, _ = A.init_population(graph, k, pop, seed=seed)
 
     def search(colors, ind_base):  # the local search, in place; returns (scores, moves)
-        if weighted:
-            o = A.wvcp_batch(graph, colors, k, iters, rounds, seed ^ SEED_TABU, ind_base=ind_base, block=block)
-            return o["best_legal"], int(o["stats"][:, 0].sum().item())
-        o = A.tabu_batch(graph, colors, k, iters, seed ^ SEED_TABU, ind_base=ind_base, block=block, table=table)
-        return o["f_best"], int(o["stats"][:, 0].sum().item())
+        rows = colors.shape[0]
+        step = slice_rows if 0 < slice_rows < rows else max(rows, 1)
+        scores, moves = [], 0
+        for r0 in range(0, rows, step):
+            part = colors[r0:r0 + step]
+            if weighted:
+                o = A.wvcp_batch(graph, part, k, iters, rounds, seed ^ SEED_TABU, ind_base=ind_base + r0,
+                                 block=block)
+                scores.append(o["best_legal"])
+            else:
+                o = A.tabu_batch(graph, part, k, iters, seed ^ SEED_TABU, ind_base=ind_base + r0, block=block,
+                                 table=table)
+                scores.append(o["f_best"])
+            moves += int(o["stats"][:, 0].sum().item())
+            if step < rows and log:
+                log(f"  local search of individuals {ind_base + r0}..{ind_base + r0 + part.shape[0] - 1} done")
+        return (scores[0] if len(scores) == 1 else torch.cat(scores)), moves
 
     f, moves = search(cols, 0)
     f = f.clone()

@@ -177,6 +177,36 @@ def test_spacing_update_reads_upper_triangle_only(dlm, dev):
     assert (pick.cpu().numpy().tolist(), int(nsp.item())) == ref
 
 
+@pytest.mark.parametrize("total,rate", [(1500, 0.0005), (1100, 0.004), (2048, 0.0)])
+def test_spacing_update_chunks(dlm, dev, total, rate):
+    """A pool of several 512-member chunks with sparse close pairs: the walk
+    stops inside a chunk, needs the fill, takes nothing or takes all; the
+    lower triangle holds garbage."""
+    rng = np.random.default_rng(19 + total)
+    close = rng.random((total, total)) < rate
+    dist = np.where(close, rng.integers(0, 11, size=(total, total)), rng.integers(11, 80, size=(total, total)))
+    dist = np.triu(dist, 1)
+    dist = dist + dist.T
+    f = rng.integers(0, 60, size=total).astype(np.int32)
+    garbage = dist.astype(np.int32)
+    garbage[np.tril_indices(total)] = -7
+    na = total // 2 + 3
+    g = cuda(garbage)
+    rows = dist.tolist()
+    for keep in (0, 1, 700, total - 1, total):
+        ref = dv.spacing_update(f, rows, keep, 10)
+        say(f"spacing update chunks total={total} keep={keep}")
+        pick, nsp = dlm.spacing_update(cuda(f[:na]), cuda(f[na:]), g, keep, 10)
+        assert (pick.cpu().numpy().tolist(), int(nsp.item())) == ref, keep
+
+
+def test_spacing_update_empty_pool(dlm, dev):
+    say("spacing update empty pool")
+    e = torch.empty(0, dtype=torch.int32, device=dev)
+    pick, nsp = dlm.spacing_update(e, e, torch.zeros((1, 1), dtype=torch.int32, device=dev), 0, 10)
+    assert pick.numel() == 0 and int(nsp.item()) == 0
+
+
 def test_nearest(dlm, dev):
     rng = np.random.default_rng(17)
     p = 150

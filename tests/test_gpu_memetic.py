@@ -217,6 +217,23 @@ def test_weighted_memetic_loop(dlm, dev, learned):
     assert (ws[legal] == res.f[legal]).all()
 
 
+def test_sliced_search_is_identical(dlm, dev):
+    """A local-search pass split into launches of fewer individuals
+    (slice_rows) gives the same loop: every individual keeps its own random
+    stream."""
+    from paper_2109_05948_amd import memetic
+    from workloads.graphs import uniform_weights
+    g = gnp(90, 0.3, seed=4)
+    g = g.with_weights(uniform_weights(90, 1, 100, seed=5))
+    G = dlm.Graph.from_csr(g)
+    say("weighted memetic sliced search")
+    runs = [memetic.run(G, 0, 32, 10 * g.n, learned=True, seed=3, cutoff_s=60, max_generations=2,
+                        scorer_params=scorer_weights(g.n, seed=0), batch=32, epochs=1, weighted=True, rounds=3,
+                        slice_rows=sr) for sr in (0, 12)]
+    assert [h[2] for h in runs[0].history] == [h[2] for h in runs[1].history]
+    assert torch.equal(runs[0].colors, runs[1].colors) and torch.equal(runs[0].f, runs[1].f)
+
+
 def test_weighted_memetic_loop_invariant_network(dlm, dev):
     """The WVCP loop learning with the paper's network at its WVCP depth
     (hidden widths 5n, 2n, n, n // 2): scores stay the weighted scores of
