@@ -53,7 +53,7 @@ KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd
 
 # HBM bytes of the two distance launches of one diversity step (old x new
 # block + new x new triangle), from the same counter runs
-DIVERSITY_TRAFFIC = {"sources_sha256": "2fe1e82053e16381f00c35f6b6a1c3b4b9f69580d74293b601c6b7f3d0aba5ce", "bytes": 1634736522}  # profiles/distance_diversity_gnp500.md
+DIVERSITY_TRAFFIC = {"sources_sha256": "9f79de36c3bbbdb83d6884a3ccb01ff45ffbb8d43bbc23bc6ed9041fc722adea", "bytes": 1629448352}  # profiles/distance_diversity_gnp500.md
 DIVERSITY_SOURCES = ("paper_2109_05948_amd/csrc/diversity.hip", "paper_2109_05948_amd/csrc/dlm_common.h")
 
 
