@@ -83,7 +83,17 @@ static int launch_w8_kq(const TabuArgs& a, int pop, int acap, size_t lds, hipStr
 static int launch_w8(const TabuArgs& a, int pop, int acap, size_t lds, hipStream_t s) {
   switch (w8_bucket(a.k)) {
     case 8: return launch_w8_kq<8>(a, pop, acap, lds, s);
-    case 16: return launch_w8_kq<16>(a, pop, acap, lds, s);
+    case 16:  // rows of 9 to 15 dwords get a kernel of their exact width
+      switch (tab_stride(a.k) >> 2) {
+        case 9: return launch_w8_kq<9>(a, pop, acap, lds, s);
+        case 10: return launch_w8_kq<10>(a, pop, acap, lds, s);
+        case 11: return launch_w8_kq<11>(a, pop, acap, lds, s);
+        case 12: return launch_w8_kq<12>(a, pop, acap, lds, s);
+        case 13: return launch_w8_kq<13>(a, pop, acap, lds, s);
+        case 14: return launch_w8_kq<14>(a, pop, acap, lds, s);
+        case 15: return launch_w8_kq<15>(a, pop, acap, lds, s);
+        default: return launch_w8_kq<16>(a, pop, acap, lds, s);
+      }
     case 24: return launch_w8_kq<24>(a, pop, acap, lds, s);
     case 32: return launch_w8_kq<32>(a, pop, acap, lds, s);
     case 64: return launch_w8_kq<64>(a, pop, acap, lds, s);

@@ -53,7 +53,7 @@ def compare(gpu, ref, ids, label):
         assert (gpu["colors"][j] == ref["colors"][j]).all(), msg
 
 
-SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords
+SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords, exact widths 9 to 15
     (37, 0.3, 4, 800, 7),
     (150, 0.5, 16, 3000, 9),
     (200, 0.1, 5, 3000, 5),
@@ -62,6 +62,10 @@ SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords
     (260, 0.8, 70, 2000, 4),
     (330, 0.9, 100, 1500, 3),
     (420, 0.95, 210, 800, 3),
+    (160, 0.5, 44, 1500, 3),  # 11 dwords
+    (140, 0.6, 47, 1500, 3),  # 12
+    (180, 0.5, 55, 1500, 3),  # 14
+    (200, 0.5, 58, 1200, 3),  # 15
 ]
 
 
