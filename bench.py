@@ -45,8 +45,8 @@ METRIC = "tabu moves/sec (population, 1 GPU) + time-to-legal-k-coloring, learned
 # --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by what the counter reads
 # for a 1 GiB device-to-device copy.  Valid only for the kernel sources they
 # were taken on (digest below) and the same table and block; otherwise null.
-MEASURED_TRAFFIC = {"sources_sha256": "4f09b9ed2f1fad9ae0aaeac31d37eb1719a58020606f0a564dd344e509626a26",
-                    "table": "wave8", "block": 64, "bytes": 27139072}  # profiles/tabucol_wave8_gnp500.md
+MEASURED_TRAFFIC = {"sources_sha256": "90f622ede0f2d30055248402ea1008c515523046e0683b22b3d379670c082e06",
+                    "table": "wave8", "block": 64, "bytes": 27144576}  # profiles/tabucol_wave8_gnp500.md
 KERNEL_SOURCES = ("paper_2109_05948_amd/csrc/tabu_body.h", "paper_2109_05948_amd/csrc/tabucol.hip",
                   "paper_2109_05948_amd/csrc/dlm_common.h", "paper_2109_05948_amd/csrc/tabu_wave.h")
 

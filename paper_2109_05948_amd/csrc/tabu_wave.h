@@ -82,8 +82,8 @@ __host__ __device__ inline W8Layout w8_layout(int n, int k, int acap) {
   return L;
 }
 
-// dwords per row bucket of the scan (rows of 9 to 15 dwords in the 16
-// bucket are launched at their exact width)
+// dwords per row bucket of the scan (rows of 9 to 15 and 17 to 23 dwords
+// are launched at their exact width)
 __host__ __device__ constexpr int w8_bucket(int k) {
   const int kq = tab_stride(k) >> 2;
   return kq <= 8 ? 8 : kq <= 16 ? 16 : kq <= 24 ? 24 : kq <= 32 ? 32 : kq <= 64 ? 64 : 0;
@@ -203,11 +203,14 @@ __device__ __forceinline__ int w8_compact_list(uint16_t* cg, uint16_t* list, int
 
 // One individual (row li of a.colors) searched by the calling wavefront.
 // KQ: dwords read per row, kp / 4 <= KQ (the exact width for rows of 9 to 15
-// dwords, else the bucket of w8_bucket); acap: tabu pairs the LDS holds.
+// and 17 to 23 dwords, else the bucket of w8_bucket); acap: tabu pairs the
+// LDS holds.
 template <int KQ>
 __device__ __forceinline__ void tabu_w8_individual(const TabuArgs& a, int li, int acap, unsigned char* smem) {
-  // KQ below 16 and not 8 is an exact row width (kq == KQ): nothing to mask
-  constexpr int KQ_LO = KQ == 8 ? 0 : KQ < 16 ? KQ : (KQ == 16 ? 8 : (KQ == 24 ? 16 : (KQ == 32 ? 24 : 32)));
+  // a bucket (8, 16, 24, 32, 64 dwords) masks what it reads past the row; any
+  // other KQ is the exact row width (kq == KQ): nothing to mask
+  constexpr bool bucket = KQ == 8 || KQ == 16 || KQ == 24 || KQ == 32 || KQ == 64;
+  constexpr int KQ_LO = !bucket ? KQ : KQ == 8 ? 0 : KQ == 16 ? 8 : KQ == 24 ? 16 : KQ == 32 ? 24 : 32;
   const int lane = threadIdx.x;
   // every field the search needs, as a value of its own: the argument block
   // as a whole (about 30 scalar registers) would otherwise stay live in, and

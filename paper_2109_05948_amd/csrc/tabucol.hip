@@ -83,7 +83,7 @@ static int launch_w8_kq(const TabuArgs& a, int pop, int acap, size_t lds, hipStr
 static int launch_w8(const TabuArgs& a, int pop, int acap, size_t lds, hipStream_t s) {
   switch (w8_bucket(a.k)) {
     case 8: return launch_w8_kq<8>(a, pop, acap, lds, s);
-    case 16:  // rows of 9 to 15 dwords get a kernel of their exact width
+    case 16:  // rows of 9 to 15 and 17 to 23 dwords get a kernel of their exact width
       switch (tab_stride(a.k) >> 2) {
         case 9: return launch_w8_kq<9>(a, pop, acap, lds, s);
         case 10: return launch_w8_kq<10>(a, pop, acap, lds, s);
@@ -94,7 +94,17 @@ static int launch_w8(const TabuArgs& a, int pop, int acap, size_t lds, hipStream
         case 15: return launch_w8_kq<15>(a, pop, acap, lds, s);
         default: return launch_w8_kq<16>(a, pop, acap, lds, s);
       }
-    case 24: return launch_w8_kq<24>(a, pop, acap, lds, s);
+    case 24:
+      switch (tab_stride(a.k) >> 2) {
+        case 17: return launch_w8_kq<17>(a, pop, acap, lds, s);
+        case 18: return launch_w8_kq<18>(a, pop, acap, lds, s);
+        case 19: return launch_w8_kq<19>(a, pop, acap, lds, s);
+        case 20: return launch_w8_kq<20>(a, pop, acap, lds, s);
+        case 21: return launch_w8_kq<21>(a, pop, acap, lds, s);
+        case 22: return launch_w8_kq<22>(a, pop, acap, lds, s);
+        case 23: return launch_w8_kq<23>(a, pop, acap, lds, s);
+        default: return launch_w8_kq<24>(a, pop, acap, lds, s);
+      }
     case 32: return launch_w8_kq<32>(a, pop, acap, lds, s);
     case 64: return launch_w8_kq<64>(a, pop, acap, lds, s);
   }

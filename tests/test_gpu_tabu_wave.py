@@ -53,7 +53,7 @@ def compare(gpu, ref, ids, label):
         assert (gpu["colors"][j] == ref["colors"][j]).all(), msg
 
 
-SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords, exact widths 9 to 15
+SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords, exact widths 9 to 15 and 17 to 23
     (37, 0.3, 4, 800, 7),
     (150, 0.5, 16, 3000, 9),
     (200, 0.1, 5, 3000, 5),
@@ -66,6 +66,12 @@ SHAPES = [  # (n, p, k, T, pop): row buckets of 8, 16, 24, 32 and 64 dwords, exa
     (140, 0.6, 47, 1500, 3),  # 12
     (180, 0.5, 55, 1500, 3),  # 14
     (200, 0.5, 58, 1200, 3),  # 15
+    (220, 0.6, 67, 1000, 3),  # 17
+    (240, 0.5, 75, 1000, 3),  # 19
+    (200, 0.7, 79, 1000, 3),  # 20
+    (260, 0.5, 83, 1000, 3),  # 21
+    (250, 0.6, 90, 1000, 3),  # 23
+    (300, 0.5, 96, 1000, 3),  # 24: the bucket at its own width
 ]
 
 
